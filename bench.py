@@ -1,0 +1,299 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the bulk PRNG-stream library on one MI355X.
+
+One step = the store-mode hot path over the bulk workload: XorShift (the
+r = 8 generator of eq. (5) and the xorshift32 of eq. (6)) and KISS, each
+producing 2^20 streams x 256 samples as uint32 and as FP32 uniforms, with
+per-stream states seeded from SplitMix64(1), read and written back every
+call.  That is 6 launches and 6 x 2^28 samples per step, inputs resident in
+HBM.  The JSON line reports whole-step GSamples/s, the roofline of the
+dominant kernel (HBM bytes from live HIP events), the measured write-only
+ceiling, side workloads (MWC32 4096 x 1024, jump-ahead split of 2^30
+samples, fused pi over 2^34 KISS samples), and the serial CPU oracle timed
+on a bounded sample.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extra]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0           # MI355X HBM3E, 8 TB/s
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9  # int32 lane-ops/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+
+S_BULK, N_BULK = 1 << 20, 256
+STEP_GENS = ["XS256", "XS32", "KISS"]
+STEP_DTYPES = ["u32", "f32"]
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--no-extra", action="store_true", help="skip the side workloads")
+    p.add_argument("--cpu-seconds", type=float, default=12.0)
+    return p.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; --gpus %d is not supported "
+              "(streams shard across GPUs with no exchange; see DESIGN.md)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1101_1846_amd as R
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    R.rng_init()
+    stream = torch.cuda.current_stream()
+
+    # ---------------------------------------------------------------- inputs
+    states = {}
+    for name in STEP_GENS:
+        g = R.GENERATORS[name]
+        st = torch.empty((R.rng_state_words(g), S_BULK), dtype=torch.int32, device=dev)
+        R.rng_seed(g, 1, 0, S_BULK, st)
+        states[name] = st
+    out = torch.empty(S_BULK * N_BULK, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+
+    launches = [(n, d) for n in STEP_GENS for d in STEP_DTYPES]
+
+    def step(events=None):
+        for i, (name, d) in enumerate(launches):
+            if events is not None:
+                events[i][0].record(stream)
+            R.rng_generate(R.GENERATORS[name], states[name], S_BULK, N_BULK, R.DTYPES[d], out)
+            if events is not None:
+                events[i][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+           for _ in launches] for _ in range(K)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    for k in range(K):
+        step(ev[k])
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = t0.elapsed_time(t1)
+    samples_per_step = len(launches) * S_BULK * N_BULK
+    value = samples_per_step * K / (ms_total * 1e-3) / 1e9
+
+    # per-kernel durations from the live events
+    per = {}
+    for i, (name, d) in enumerate(launches):
+        durs = [ev[k][i][0].elapsed_time(ev[k][i][1]) for k in range(K)]
+        W = R.rng_state_words(R.GENERATORS[name])
+        bytes_alg = S_BULK * N_BULK * 4 + 2 * S_BULK * W * 4
+        mean_ms = float(np.mean(durs))
+        per["%s_%s" % (name, d)] = {
+            "ms": round(mean_ms, 4),
+            "GSamples_s": round(S_BULK * N_BULK / (mean_ms * 1e-3) / 1e9, 2),
+            "GB_s": round(bytes_alg / (mean_ms * 1e-3) / 1e9, 1),
+            "bytes": bytes_alg,
+            "total_ms": float(np.sum(durs)),
+        }
+    dom_key = max(per, key=lambda k: per[k]["total_ms"])
+    dom = per[dom_key]
+    achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
+
+    # ------------------------------------------------- measured write ceiling
+    ceil = write_ceiling(torch, dev)
+
+    extra = {} if args.no_extra else side_workloads(torch, R, dev, stream)
+
+    cpu = None if args.no_cpu else cpu_baseline(args.cpu_seconds)
+
+    line = {
+        "metric": "GSamples/s & HBM write GB/s (% peak), bit-exact; batched p50/p99 latency",
+        "value": round(value, 2),
+        "unit": "GSamples/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_total / K, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic: per-stream states from SplitMix64(seed=1), no dataset",
+        "config": {
+            "workload": "bulk store mode: XS256 (eq. 5), XS32 (eq. 6), KISS; 2^20 streams x 256 samples; "
+                        "uint32 and FP32 (u>>8)*2^-24 outputs; state read+write-back per call",
+            "streams": S_BULK, "samples_per_stream": N_BULK, "launches_per_step": len(launches),
+            "samples_per_step": samples_per_step, "parallelism": "single GPU",
+        },
+        "hbm_write_GB_s": round(samples_per_step * 4 * K / (ms_total * 1e-3) / 1e9, 1),
+        "frac_hbm_peak": round(samples_per_step * 4 * K / (ms_total * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "roofline": {
+            "kernel": "k_generate<%s> (store mode)" % dom_key,
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": None,
+            "bytes_per_launch": dom["bytes"],
+            "avg_launch_ms": dom["ms"],
+        },
+        "write_ceiling": ceil,
+        "frac_of_write_ceiling": round(achieved / ceil["best_GB_s"], 4) if ceil else None,
+        "per_kernel": {k: {kk: vv for kk, vv in v.items() if kk != "total_ms"} for k, v in per.items()},
+        "side_workloads": extra,
+        "cpu_baseline": cpu,
+        "wall_s_timed": round(wall, 3),
+    }
+    print(json.dumps(line))
+
+
+def write_ceiling(torch, dev):
+    """Write-only bandwidth of plain fills over 4 GiB (torch's fill kernel and
+    hipMemsetD32), the paper's own practice of measuring the achievable rate."""
+    import ctypes
+    n = 1 << 30
+    buf = torch.empty(n, dtype=torch.int32, device=dev)
+    res = {}
+    for _ in range(2):
+        buf.fill_(7)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        buf.fill_(7)
+    e1.record()
+    torch.cuda.synchronize()
+    res["torch_fill_GB_s"] = round(4 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    try:
+        hip = ctypes.CDLL("libamdhip64.so")
+        hip.hipMemsetD32Async.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_void_p]
+        s = torch.cuda.current_stream().cuda_stream
+        for _ in range(2):
+            hip.hipMemsetD32Async(buf.data_ptr(), 5, n, s)
+        e0.record()
+        for _ in range(reps):
+            hip.hipMemsetD32Async(buf.data_ptr(), 5, n, s)
+        e1.record()
+        torch.cuda.synchronize()
+        res["hipMemsetD32_GB_s"] = round(4 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    except OSError:
+        pass
+    res["best_GB_s"] = max(v for k, v in res.items() if k.endswith("GB_s"))
+    res["bytes"] = 4 * n
+    del buf
+    torch.cuda.empty_cache()
+    return res
+
+
+def _time(torch, fn, reps):
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def side_workloads(torch, R, dev, stream):
+    res = {}
+    # MWC32, 4096 streams x 1024 (small, launch-bound; chunked by jump-ahead)
+    g = R.RNG_MWC32
+    S, N = 4096, 1024
+    st = torch.empty((2, S), dtype=torch.int32, device=dev)
+    R.rng_seed(g, 0, 0, S, st)
+    o = torch.empty(S * N, dtype=torch.int32, device=dev)
+    ms = _time(torch, lambda: R.rng_generate(g, st, S, N, R.RNG_U32, o), 200)
+    res["mwc32_4096x1024"] = {"us_per_call": round(ms * 1e3, 2),
+                              "GSamples_s": round(S * N / (ms * 1e-3) / 1e9, 1)}
+    # MWC1616 and MWC32 at the bulk size
+    for name in ("MWC1616", "MWC32"):
+        g = R.GENERATORS[name]
+        st = torch.empty((R.rng_state_words(g), S_BULK), dtype=torch.int32, device=dev)
+        R.rng_seed(g, 1, 0, S_BULK, st)
+        o = torch.empty(S_BULK * N_BULK, dtype=torch.int32, device=dev)
+        for dname, d in R.DTYPES.items():
+            ms = _time(torch, lambda: R.rng_generate(g, st, S_BULK, N_BULK, d, o), 10)
+            res["%s_bulk_%s" % (name, dname)] = {"ms": round(ms, 4),
+                                                  "GSamples_s": round(S_BULK * N_BULK / (ms * 1e-3) / 1e9, 1)}
+        del o
+    # jump-ahead split of one 2^30-sample sequence over 2^20 threads
+    total, T = 1 << 30, 1 << 20
+    o = torch.empty(total, dtype=torch.int32, device=dev)
+    for name in ("MWC32", "XS256"):
+        g = R.GENERATORS[name]
+        W = R.rng_state_words(g)
+        s1 = torch.empty(W, dtype=torch.int32, device=dev)
+        R.rng_seed(g, 2, 0, 1, s1)
+        fin = torch.empty(W, dtype=torch.int32, device=dev)
+        wsb = R.rng_split_workspace_bytes(g, T)
+        ws = torch.empty(wsb // 4, dtype=torch.int32, device=dev)
+        ms = _time(torch, lambda: R.rng_generate_split(g, s1, total, T, R.RNG_U32, o, fin, ws, wsb), 5)
+        res["split_2^30_%s" % name] = {"ms": round(ms, 3),
+                                       "GSamples_s": round(total / (ms * 1e-3) / 1e9, 1),
+                                       "GB_s": round(4 * total / (ms * 1e-3) / 1e9, 1)}
+    del o
+    # fused pi over 2^34 KISS samples (no stores: integer-VALU bound)
+    g = R.RNG_KISS
+    S, N = 1 << 20, 1 << 14
+    st = torch.empty((6, S), dtype=torch.int32, device=dev)
+    R.rng_seed(g, 6, 0, S, st)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    ms = _time(torch, lambda: R.rng_fused_pi(g, st, S, N, cnt), 5)
+    res["fused_pi_kiss_2^34"] = {"ms": round(ms, 3), "GSamples_s": round(S * N / (ms * 1e-3) / 1e9, 1)}
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(seconds):
+    """The serial oracle on the host's cores over a bounded sample of the step's
+    workload (whole streams of 256 samples, every generator and dtype of the
+    step), scaled to GSamples/s."""
+    import numpy as np
+
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    gens = [(oracle.GENERATORS[n], d) for n in STEP_GENS for d in (oracle.U32, oracle.F32)]
+
+    def run(S):
+        t = time.perf_counter()
+        for g, d in gens:
+            st = oracle.seed(g, 1, S)
+            oracle.generate(g, st, N_BULK, d, threads=threads)
+        return time.perf_counter() - t
+
+    S = 1 << 12
+    dt = run(S)
+    S = int(min(S_BULK, max(S, S * seconds / max(dt, 1e-3))))
+    S = max(threads, S // threads * threads)
+    dt = run(S)
+    samples = len(gens) * S * N_BULK
+    return {"value": round(samples / dt / 1e9, 4), "unit": "GSamples/s", "cores": threads, "kind": "oracle",
+            "sample": "%d streams x %d samples for each of %d (generator, dtype) pairs of the step "
+                      "(%.1f s of CPU wall time)" % (S, N_BULK, len(gens), dt)}
+
+
+if __name__ == "__main__":
+    main()

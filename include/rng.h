@@ -1,0 +1,153 @@
+/*
+ * rng.h -- C ABI of the MI355X bulk pseudo-random stream library.
+ *
+ * The library generates many independent 32-bit streams of the recurrences
+ * studied in Hissoiny, Despres & Ozell, "Using graphics processing units to
+ * generate random numbers" (arXiv:1101.1846):
+ *   RNG_MWC32   multiply-with-carry, eq. (2)-(3), base b = 2^32, multiplier
+ *               a = 65274 (the largest a < 2^16 with a*b - 1 a safe prime,
+ *               the rule of Sec. II.A.1; the paper prints no value);
+ *   RNG_MWC1616 the paper's MWC of Sec. III.A.1: two base-2^16 MWCs with
+ *               distinct multipliers from the 392-entry safe-prime table,
+ *               output (z << 16) + w;
+ *   RNG_XS256   Panneton's r = 8, w = 32 XorShift, eq. (5), period 2^256 - 1;
+ *   RNG_XS32    Marsaglia's xorshift32, eq. (6): y ^= y<<13; y ^= y>>17;
+ *               y ^= y<<5;
+ *   RNG_KISS    Sec. II.A.3: (MWC1616 xor LCG) + XS32, with the LCG of eq. (7)
+ *               X <- 69069 X + 1234567 mod 2^32.
+ * Every output is the value after a step ("step, then emit", eq. (1)); the
+ * seed itself is never emitted.
+ *
+ * Conventions common to all calls
+ *  - Pointers named d_* are device (HBM) pointers on the current HIP device;
+ *    h_* are host pointers.  The caller allocates and frees every state and
+ *    output buffer; the library never frees memory it did not allocate.
+ *  - State layout (the paper keeps per-thread seeds and multipliers in global
+ *    memory, fetched coalesced, Sec. III.A.1): structure of arrays, word w of
+ *    stream s at d_state[w * n_streams + s].  Words per stream:
+ *      MWC32 2 (x, c)   MWC1616 4 (z, w, a1, a2)   XS256 8 (v0..v7, v0 oldest)
+ *      XS32 1 (y)       KISS 6 (z, w, jsr, jcong, a1, a2)
+ *    State arrays are in/out: every generating call writes the advanced state
+ *    back (the paper includes this write-back in its timing, Sec. III.B).
+ *  - Output layout: stream-major, sample k of stream s at d_out[s * n + k]
+ *    (the paper's output pool, Sec. III.B, whose layout it leaves open).
+ *    RNG_U32 writes uint32 values; RNG_F32 writes float (u >> 8) * 2^-24,
+ *    exact, in [0, 1 - 2^-24] (the [0,1) uniforms of Sec. III.B with the
+ *    scaling fixed to the top 24 bits so that the map is exact).
+ *  - Asynchrony: work is queued on the HIP stream passed as void*
+ *    (hipStream_t, NULL = the null stream) and the call returns without
+ *    waiting; argument checks happen before anything is queued.
+ *  - Errors: 0 on success, a negative RNG_E* code otherwise; no exception
+ *    crosses the ABI.  rng_strerror() describes a code, rng_last_error()
+ *    gives the message of the calling thread's last failure.
+ *  - Device tables (multiplier table, jump-ahead power tables) are built on
+ *    the host and uploaded once per device, lazily on first use or by
+ *    rng_init(); they are owned by the library until rng_shutdown().
+ */
+#ifndef RNG_MI355X_H
+#define RNG_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { RNG_MWC32 = 1, RNG_XS256 = 2, RNG_XS32 = 3, RNG_KISS = 4, RNG_MWC1616 = 5 } rng_gen_t;
+typedef enum { RNG_U32 = 0, RNG_F32 = 1 } rng_dtype_t;
+
+#define RNG_OK 0
+#define RNG_EINVAL (-1)  /* bad generator, dtype, null pointer or misaligned pointer */
+#define RNG_ERANGE (-2)  /* a size or a size product overflows, or exceeds a limit */
+#define RNG_ENOMEM (-3)  /* admission or workspace too small / allocation failed */
+#define RNG_EHIP (-4)    /* a HIP runtime call failed; see rng_last_error() */
+#define RNG_ENODEV (-5)  /* no usable gfx950 device */
+#define RNG_EAGAIN (-6)  /* not ready yet (server polling) */
+
+const char *rng_strerror(int code);
+const char *rng_last_error(void);
+
+/* Build and upload the device tables for the current device (idempotent). */
+int rng_init(void);
+/* Free the device tables of every device the library touched. */
+int rng_shutdown(void);
+
+/* Number of 32-bit state words per stream for generator g. */
+int rng_state_words(int g, uint32_t *words);
+
+/* The MWC32 multiplier (65274) and the 392 base-2^16 multipliers, ascending
+ * (Sec. III.A.1).  h_out must hold cap entries; *count receives 392. */
+int rng_mwc32_multiplier(uint32_t *a);
+int rng_mwc16_multipliers(uint16_t *h_out, uint32_t cap, uint32_t *count);
+
+/* Seed n_streams states from SplitMix64(seed) (Steele, Lea & Flood 2014).
+ * Stream s uses the SplitMix64 outputs D*(first_stream+s) ... +D-1 with
+ * D = 1 (MWC32, XS32), 2 (MWC1616), 3 (KISS), 4 (XS256); each stream gets its
+ * own seeds and, for MWC1616/KISS, its own multiplier pair: the paper's
+ * parametrisation plus independent seeds (Sec. II.A.4, III.A.1, III.A.3).
+ * Fixed points are avoided: MWC c < a and z = c*b + x not in {0, a*b - 1};
+ * XorShift states non-zero.  d_state: [words][n_streams] uint32, written. */
+int rng_seed(int g, uint64_t seed, uint64_t first_stream, uint64_t n_streams,
+             uint32_t *d_state, void *stream);
+
+/* Bulk generation, Sec. III.A / III.B: n_streams streams, n samples each.
+ * d_state [words][n_streams] in/out; d_out [n_streams][n] of dtype t, 4-byte
+ * aligned (16-byte alignment with n % 4 == 0 takes 128-bit stores).
+ * n = 0 or n_streams = 0 is a no-op.  When n_streams is small the library
+ * splits each stream into chunks that start from jumped-ahead states, so the
+ * output is still the serial sequence of every stream. */
+int rng_generate(int g, uint32_t *d_state, uint64_t n_streams, uint64_t n, int t,
+                 void *d_out, void *stream);
+
+/* Same, with an explicit launch shape: wg in {64,128,256,512,1024} lanes per
+ * workgroup and unroll in {1,2,4,8,16} samples per generation-loop step.
+ * rng_generate uses the autotuned shape when one is loaded, else a default. */
+int rng_generate_ex(int g, uint32_t *d_state, uint64_t n_streams, uint64_t n, int t,
+                    void *d_out, uint32_t wg, uint32_t unroll, void *stream);
+
+/* Launch shape used by rng_generate for (g, t): set, read, or pick by timing
+ * every (wg, unroll) pair on the given problem (d_state_scratch and
+ * d_out_scratch are overwritten; reps timed launches per shape).  The paper
+ * chose block sizes with an occupancy calculator and unrolled its main loop
+ * (Sec. III.A.1, III.B); the choice here is measured. */
+int rng_set_shape(int g, int t, uint32_t wg, uint32_t unroll);
+int rng_get_shape(int g, int t, uint32_t *wg, uint32_t *unroll);
+int rng_autotune(int g, int t, uint64_t n_streams, uint64_t n, uint32_t *d_state_scratch,
+                 void *d_out_scratch, uint32_t reps, uint32_t *best_wg, uint32_t *best_unroll,
+                 float *best_us, void *stream);
+
+/* Advance every stream by k steps without producing output: sequence
+ * splitting needs the i-th number without the intermediate ones (Sec.
+ * II.A.4).  MWC: z <- a^k z mod (a*b - 1) with z = c*b + x; XorShift: the
+ * k-th power of the GF(2) step matrix; LCG: the k-fold affine map. */
+int rng_skip(int g, uint32_t *d_state, uint64_t n_streams, uint64_t k, void *stream);
+
+/* Sequence splitting (Sec. II.A.4): one logical stream, d_state_one
+ * ([words] uint32, device, read only), produces `total` samples divided
+ * across n_threads GPU threads, thread t writing samples
+ * [t*C, min((t+1)*C, total)) with C = ceil(total / n_threads), each thread
+ * starting from the jumped-ahead state, so that d_out[0 .. total) equals the
+ * serial sequence.  The advanced state is written to d_final_state ([words],
+ * device; may alias d_state_one).  d_workspace of at least
+ * rng_split_workspace_bytes(g, n_threads) bytes, 256-byte aligned, caller
+ * owned, holds the per-thread states. */
+int rng_split_workspace_bytes(int g, uint64_t n_threads, uint64_t *bytes);
+int rng_generate_split(int g, const uint32_t *d_state_one, uint64_t total, uint64_t n_threads,
+                       int t, void *d_out, uint32_t *d_final_state, void *d_workspace,
+                       uint64_t workspace_bytes, void *stream);
+
+/* Fused consumer (the paper's "without write-back" mode, Sec. III.B, made to
+ * consume every sample): each stream draws n samples; consecutive pairs
+ * (u_{2k}, u_{2k+1}) give i = u_{2k} >> 8, j = u_{2k+1} >> 8 and count when
+ * i^2 + j^2 < 2^48, i.e. x^2 + y^2 < 1 exactly for the FP32 uniforms
+ * x = i 2^-24, y = j 2^-24.  The count of all streams is ADDED to *d_count
+ * (device uint64; clear it first).  No sample is stored; states are written
+ * back.  An odd trailing sample is drawn but not counted. */
+int rng_fused_pi(int g, uint32_t *d_state, uint64_t n_streams, uint64_t n,
+                 uint64_t *d_count, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RNG_MI355X_H */

@@ -1,0 +1,6 @@
+// Kernel instantiations for the KISS generator.
+#include "rng_kernels.hpp"
+
+namespace rngx {
+RNGX_INSTANTIATE(GenKISS)
+}  // namespace rngx

@@ -1,0 +1,6 @@
+// Kernel instantiations for the MWC1616 generator.
+#include "rng_kernels.hpp"
+
+namespace rngx {
+RNGX_INSTANTIATE(GenMWC1616)
+}  // namespace rngx

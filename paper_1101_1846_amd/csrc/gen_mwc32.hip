@@ -1,0 +1,6 @@
+// Kernel instantiations for the MWC32 generator.
+#include "rng_kernels.hpp"
+
+namespace rngx {
+RNGX_INSTANTIATE(GenMWC32)
+}  // namespace rngx

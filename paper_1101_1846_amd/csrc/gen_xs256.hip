@@ -1,0 +1,6 @@
+// Kernel instantiations for the XS256 generator.
+#include "rng_kernels.hpp"
+
+namespace rngx {
+RNGX_INSTANTIATE(GenXS256)
+}  // namespace rngx

@@ -1,0 +1,6 @@
+// Kernel instantiations for the XS32 generator.
+#include "rng_kernels.hpp"
+
+namespace rngx {
+RNGX_INSTANTIATE(GenXS32)
+}  // namespace rngx

@@ -1,0 +1,59 @@
+// host_math.hpp -- host-side number theory and GF(2) algebra that the
+// library needs before it can launch anything: the multiplier tables, the
+// MWC32 multiplier, and the jump-ahead power tables uploaded to the device.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+namespace rngx {
+
+constexpr int kMwc16Count = 392;  // Sec. III.A.1 counts 392 base-2^16 multipliers
+constexpr int kPowBits = 64;      // jump distances are 64-bit
+
+// 64-bit modular arithmetic (exact, via 128-bit products).
+uint64_t mulmod64(uint64_t a, uint64_t b, uint64_t m);
+uint64_t powmod64(uint64_t a, uint64_t e, uint64_t m);
+bool is_prime_u64(uint64_t n);  // deterministic Miller-Rabin for all 64-bit n
+
+// Safe-prime multiplier rule of Sec. II.A.1: a*b - 1 and (a*b - 2)/2 prime.
+const std::vector<uint16_t> &mwc16_multipliers();  // 392 entries, ascending
+uint32_t mwc32_multiplier();                         // largest a < 2^16 for b = 2^32
+
+// A W-word GF(2)-linear state map (W = 1 for xorshift32, 8 for the r = 8
+// XorShift of eq. (5)), stored column-major: col(b) is the image of the unit
+// state with only bit b set (bit b = bit b%32 of word b/32).
+template <int W>
+struct Gf2Mat {
+    uint32_t c[32 * W][W];
+    static Gf2Mat identity();
+    void apply(const uint32_t *in, uint32_t *out) const;
+    Gf2Mat operator*(const Gf2Mat &rhs) const;  // (this * rhs) x = this(rhs(x))
+    bool operator==(const Gf2Mat &o) const;
+};
+
+Gf2Mat<8> xs256_step_matrix();  // eq. (5)
+Gf2Mat<1> xs32_step_matrix();   // eq. (6)
+
+// Device-side jump tables, written once per device.  All multiplicative
+// constants are stored in the "fold" domain used by the device modular
+// multiply (see rng_device.hpp): MWC32 constants pre-multiplied by 2^64 mod m,
+// MWC16 constants by 2^48 mod m_i.
+struct HostTables {
+    uint32_t mwc32_a;
+    uint64_t mwc32_m;
+    uint16_t t392[kMwc16Count];
+    uint64_t mwc32_pow_fold[kPowBits];         // a^(2^b) * 2^64 mod m
+    uint32_t lcg_pow[kPowBits][2];             // (A, C) of 2^b LCG steps
+    uint32_t xs32_pow[kPowBits][32];           // M^(2^b), 32 columns
+    uint32_t mwc16_pow_fold[kMwc16Count][kPowBits];  // a_i^(2^b) * 2^48 mod m_i
+    std::vector<uint32_t> xs256_pow;           // [64][256][8]: M^(2^b)
+};
+const HostTables &host_tables();
+
+// Fold-domain constants for an arbitrary jump distance (used by the host for
+// chunked launches; the device composes powers of two itself).
+uint64_t mwc32_fold_const(uint64_t k);
+Gf2Mat<8> xs256_pow(uint64_t k);
+
+}  // namespace rngx

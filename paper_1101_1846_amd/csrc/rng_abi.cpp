@@ -1,0 +1,481 @@
+// rng_abi.cpp -- the C ABI declared in include/rng.h: argument checks,
+// per-device tables, launch-shape selection, and the call sequences of the
+// multi-kernel operations (sequence splitting).
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "host_math.hpp"
+#include "rng.h"
+#include "rng_abi_internal.hpp"
+#include "rng_internal.hpp"
+
+namespace rngx {
+
+static thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(RNG_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------- tables
+namespace {
+constexpr int kMaxDev = 64;
+struct DevEntry {
+    bool ready = false;
+    void *blob = nullptr;
+    DevTables tab{};
+};
+std::mutex g_mu;
+DevEntry g_dev[kMaxDev];
+}  // namespace
+
+int device_tables(DevTables *out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDev) return fail(RNG_ENODEV, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevEntry &d = g_dev[dev];
+    if (!d.ready) {
+        hipDeviceProp_t prop;
+        if ((e = hipGetDeviceProperties(&prop, dev)) != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+            return fail(RNG_ENODEV, "device %d is %s; this library is built for gfx950", dev, prop.gcnArchName);
+        const HostTables &H = host_tables();
+        const size_t o_t392 = 0, n_t392 = sizeof(H.t392);
+        const size_t o_m32 = 1024, n_m32 = sizeof(H.mwc32_pow_fold);
+        const size_t o_lcg = o_m32 + 1024, n_lcg = sizeof(H.lcg_pow);
+        const size_t o_x32 = o_lcg + 1024, n_x32 = sizeof(H.xs32_pow);
+        const size_t o_m16 = o_x32 + n_x32, n_m16 = sizeof(H.mwc16_pow_fold);
+        const size_t o_x256 = (o_m16 + n_m16 + 255) & ~(size_t)255;
+        const size_t n_x256 = H.xs256_pow.size() * sizeof(uint32_t);
+        const size_t total = o_x256 + n_x256;
+        std::string host(total, '\0');
+        std::memcpy(&host[o_t392], H.t392, n_t392);
+        std::memcpy(&host[o_m32], H.mwc32_pow_fold, n_m32);
+        std::memcpy(&host[o_lcg], H.lcg_pow, n_lcg);
+        std::memcpy(&host[o_x32], H.xs32_pow, n_x32);
+        std::memcpy(&host[o_m16], H.mwc16_pow_fold, n_m16);
+        std::memcpy(&host[o_x256], H.xs256_pow.data(), n_x256);
+        void *blob = nullptr;
+        if ((e = hipMalloc(&blob, total)) != hipSuccess) return hip_fail(e, "hipMalloc(tables)");
+        if ((e = hipMemcpy(blob, host.data(), total, hipMemcpyHostToDevice)) != hipSuccess) {
+            (void)hipFree(blob);
+            return hip_fail(e, "hipMemcpy(tables)");
+        }
+        char *b = (char *)blob;
+        d.tab.t392 = (const uint16_t *)(b + o_t392);
+        d.tab.mwc32_pow = (const uint64_t *)(b + o_m32);
+        d.tab.lcg_pow = (const uint32_t *)(b + o_lcg);
+        d.tab.xs32_pow = (const uint32_t *)(b + o_x32);
+        d.tab.mwc16_pow = (const uint32_t *)(b + o_m16);
+        d.tab.xs256_pow = (const uint32_t *)(b + o_x256);
+        d.tab.mwc32_a = H.mwc32_a;
+        d.tab.mwc32_m = H.mwc32_m;
+        d.blob = blob;
+        d.ready = true;
+    }
+    *out = d.tab;
+    return RNG_OK;
+}
+
+int shutdown_tables()
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (int i = 0; i < kMaxDev; ++i) {
+        if (!g_dev[i].ready) continue;
+        (void)hipSetDevice(i);
+        (void)hipFree(g_dev[i].blob);
+        g_dev[i] = DevEntry();
+    }
+    (void)hipSetDevice(cur);
+    return RNG_OK;
+}
+
+// ---------------------------------------------------------------- shapes
+int gen_words(int g)
+{
+    switch (g) {
+    case RNG_MWC32: return 2;
+    case RNG_XS256: return 8;
+    case RNG_XS32: return 1;
+    case RNG_KISS: return 6;
+    case RNG_MWC1616: return 4;
+    }
+    return 0;
+}
+
+static std::mutex g_shape_mu;
+static Shape g_shape[6][2] = {};
+
+Shape tuned_shape(int g, int dt)
+{
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    Shape s = g_shape[g][dt];
+    if (!s.wg) s = Shape{256, 8};
+    return s;
+}
+
+void set_tuned_shape(int g, int dt, Shape s)
+{
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    g_shape[g][dt] = s;
+}
+
+bool valid_shape(uint32_t wg, uint32_t unroll)
+{
+    return (wg == 64 || wg == 128 || wg == 256 || wg == 512 || wg == 1024) &&
+           (unroll == 1 || unroll == 2 || unroll == 4 || unroll == 8 || unroll == 16);
+}
+
+// Smallest chunk worth a jump: the jump costs a few modular multiplies for
+// MWC/LCG words and 32x32 mat-vecs for xorshift32, but 256x256 mat-vecs for
+// the r = 8 XorShift.
+static uint64_t min_chunk(int g)
+{
+    switch (g) {
+    case RNG_MWC32: return 64;
+    case RNG_XS32: return 128;
+    case RNG_MWC1616: return 128;
+    case RNG_KISS: return 256;
+    case RNG_XS256: return 4096;
+    }
+    return 1u << 30;
+}
+
+// Split each stream into P chunks when there are too few streams to fill the
+// chip (256 CUs x 4 SIMDs; aim for >= 2 waves per SIMD).
+void choose_chunks(int g, uint64_t S, uint64_t N, uint64_t align, uint64_t *C, uint32_t *P)
+{
+    const uint64_t target_lanes = (uint64_t)1 << 17;
+    uint64_t p = 1;
+    while (S * p * 2 <= target_lanes && N / (p * 2) >= min_chunk(g)) p *= 2;
+    if (p == 1) {
+        *C = N;
+        *P = 1;
+        return;
+    }
+    uint64_t c = (N + p - 1) / p;
+    c = (c + align - 1) / align * align;
+    *C = c;
+    *P = (uint32_t)((N + c - 1) / c);
+}
+
+int dispatch_generate(int g, int dt, const GenArgs &a, int wg, int unroll, bool staged, hipStream_t st)
+{
+    switch (g) {
+    case RNG_MWC32: return launch_generate_t<GenMWC32>(dt, a, wg, unroll, staged, st);
+    case RNG_XS256: return launch_generate_t<GenXS256>(dt, a, wg, unroll, staged, st);
+    case RNG_XS32: return launch_generate_t<GenXS32>(dt, a, wg, unroll, staged, st);
+    case RNG_KISS: return launch_generate_t<GenKISS>(dt, a, wg, unroll, staged, st);
+    case RNG_MWC1616: return launch_generate_t<GenMWC1616>(dt, a, wg, unroll, staged, st);
+    }
+    return -2;
+}
+
+#define RNGX_GEN_SWITCH(g, call)                                        \
+    switch (g) {                                                        \
+    case RNG_MWC32: { using G = GenMWC32; return call; }                \
+    case RNG_XS256: { using G = GenXS256; return call; }                \
+    case RNG_XS32: { using G = GenXS32; return call; }                  \
+    case RNG_KISS: { using G = GenKISS; return call; }                  \
+    case RNG_MWC1616: { using G = GenMWC1616; return call; }            \
+    }                                                                   \
+    return -2;
+
+int dispatch_seed(int g, uint64_t seed, uint64_t first, uint64_t S, uint32_t *st, const DevTables &tab,
+                  hipStream_t s)
+{
+    RNGX_GEN_SWITCH(g, launch_seed_t<G>(seed, first, S, st, tab, s))
+}
+
+int dispatch_skip(int g, uint32_t *st, uint64_t S, uint64_t k, const DevTables &tab, hipStream_t s)
+{
+    RNGX_GEN_SWITCH(g, launch_skip_t<G>(st, S, k, tab, s))
+}
+
+int dispatch_tree_level(int g, uint32_t *ws, uint64_t T, uint64_t lo, uint64_t dist, const DevTables &tab,
+                        hipStream_t s)
+{
+    RNGX_GEN_SWITCH(g, launch_tree_level_t<G>(ws, T, lo, dist, tab, s))
+}
+
+int dispatch_state_copy(int g, const uint32_t *src, uint64_t ss, uint64_t si, uint32_t *dst, uint64_t ds,
+                        uint64_t di, hipStream_t s)
+{
+    RNGX_GEN_SWITCH(g, launch_state_copy_t<G>(src, ss, si, dst, ds, di, s))
+}
+
+int dispatch_fused(int g, const FusedArgs &a, hipStream_t s)
+{
+    RNGX_GEN_SWITCH(g, launch_fused_pi_t<G>(a, s))
+}
+
+int check_launch(int rc, const char *what)
+{
+    if (rc == 0) return RNG_OK;
+    if (rc == -2) return fail(RNG_EINVAL, "%s: unsupported launch shape", what);
+    hipError_t e = hipGetLastError();
+    return fail(RNG_EHIP, "%s: launch failed: %s", what, hipGetErrorString(e));
+}
+
+static bool mul_overflows(uint64_t a, uint64_t b, uint64_t *r)
+{
+    return __builtin_mul_overflow(a, b, r);
+}
+
+// Shared by rng_generate and the split path: one generate launch over
+// S streams whose states live at stride ld.
+int generate_impl(int g, int dt, uint32_t *d_state, uint64_t ld, uint64_t S, uint64_t N, void *d_out,
+                  Shape shape, bool staged, hipStream_t st)
+{
+    if (S == 0 || N == 0) return RNG_OK;
+    DevTables tab;
+    int rc = device_tables(&tab);
+    if (rc) return rc;
+    GenArgs a{};
+    a.state = d_state;
+    a.ld = ld;
+    a.S = S;
+    a.N = N;
+    a.out = d_out;
+    a.vec4 = (N % 4 == 0) && (((uintptr_t)d_out & 15) == 0);
+    a.nt = 1;
+    a.tab = tab;
+    choose_chunks(g, S, N, kGenTile, &a.C, &a.P);
+    return check_launch(dispatch_generate(g, dt, a, (int)shape.wg, (int)shape.unroll, staged, st),
+                        "rng_generate");
+}
+
+int check_gen(int g) { return gen_words(g) ? RNG_OK : fail(RNG_EINVAL, "unknown generator %d", g); }
+
+int check_sizes(uint64_t S, uint64_t N, uint64_t words)
+{
+    uint64_t t;
+    if (mul_overflows(S, N, &t) || mul_overflows(t, 4, &t))
+        return fail(RNG_ERANGE, "n_streams * n * 4 overflows 64 bits");
+    if (mul_overflows(S, words, &t) || mul_overflows(t, 4, &t))
+        return fail(RNG_ERANGE, "state size overflows 64 bits");
+    // keeps every grid below 2^31 workgroups (64-lane groups, <= 2^30 waves)
+    if (S > ((uint64_t)1 << 36)) return fail(RNG_ERANGE, "n_streams above 2^36");
+    return RNG_OK;
+}
+
+}  // namespace rngx
+
+using namespace rngx;
+
+// ====================================================================== ABI
+extern "C" {
+
+const char *rng_strerror(int code)
+{
+    switch (code) {
+    case RNG_OK: return "success";
+    case RNG_EINVAL: return "invalid argument";
+    case RNG_ERANGE: return "size out of range";
+    case RNG_ENOMEM: return "insufficient memory or workspace";
+    case RNG_EHIP: return "HIP runtime error";
+    case RNG_ENODEV: return "no usable gfx950 device";
+    case RNG_EAGAIN: return "not ready";
+    }
+    return "unknown error";
+}
+
+const char *rng_last_error(void) { return g_last_error.c_str(); }
+
+int rng_init(void)
+{
+    DevTables t;
+    return device_tables(&t);
+}
+
+int rng_shutdown(void) { return shutdown_tables(); }
+
+int rng_state_words(int g, uint32_t *words)
+{
+    if (check_gen(g)) return RNG_EINVAL;
+    if (!words) return fail(RNG_EINVAL, "words is NULL");
+    *words = (uint32_t)gen_words(g);
+    return RNG_OK;
+}
+
+int rng_mwc32_multiplier(uint32_t *a)
+{
+    if (!a) return fail(RNG_EINVAL, "a is NULL");
+    *a = mwc32_multiplier();
+    return RNG_OK;
+}
+
+int rng_mwc16_multipliers(uint16_t *h_out, uint32_t cap, uint32_t *count)
+{
+    if (!count) return fail(RNG_EINVAL, "count is NULL");
+    const auto &t = mwc16_multipliers();
+    *count = (uint32_t)t.size();
+    if (h_out) {
+        if (cap < t.size()) return fail(RNG_ERANGE, "cap %u < %zu", cap, t.size());
+        std::memcpy(h_out, t.data(), t.size() * sizeof(uint16_t));
+    }
+    return RNG_OK;
+}
+
+int rng_seed(int g, uint64_t seed, uint64_t first_stream, uint64_t n_streams, uint32_t *d_state,
+             void *stream)
+{
+    if (check_gen(g)) return RNG_EINVAL;
+    if (n_streams == 0) return RNG_OK;
+    if (!d_state) return fail(RNG_EINVAL, "d_state is NULL");
+    if ((uintptr_t)d_state & 3) return fail(RNG_EINVAL, "d_state not 4-byte aligned");
+    if (int rc = check_sizes(n_streams, 1, gen_words(g))) return rc;
+    uint64_t end;
+    if (__builtin_add_overflow(first_stream, n_streams, &end) ||
+        mul_overflows(end, 4, &end))
+        return fail(RNG_ERANGE, "first_stream + n_streams too large");
+    DevTables tab;
+    if (int rc = device_tables(&tab)) return rc;
+    return check_launch(dispatch_seed(g, seed, first_stream, n_streams, d_state, tab, (hipStream_t)stream),
+                        "rng_seed");
+}
+
+int rng_generate_ex(int g, uint32_t *d_state, uint64_t n_streams, uint64_t n, int t, void *d_out,
+                    uint32_t wg, uint32_t unroll, void *stream)
+{
+    if (check_gen(g)) return RNG_EINVAL;
+    if (t != RNG_U32 && t != RNG_F32) return fail(RNG_EINVAL, "unknown dtype %d", t);
+    if (!valid_shape(wg, unroll)) return fail(RNG_EINVAL, "launch shape wg=%u unroll=%u", wg, unroll);
+    if (n_streams == 0 || n == 0) return RNG_OK;
+    if (!d_state || !d_out) return fail(RNG_EINVAL, "NULL state or output");
+    if (((uintptr_t)d_state & 3) || ((uintptr_t)d_out & 3))
+        return fail(RNG_EINVAL, "state and output must be 4-byte aligned");
+    if (int rc = check_sizes(n_streams, n, gen_words(g))) return rc;
+    return generate_impl(g, t, d_state, n_streams, n_streams, n, d_out, Shape{wg, unroll}, true,
+                         (hipStream_t)stream);
+}
+
+int rng_generate(int g, uint32_t *d_state, uint64_t n_streams, uint64_t n, int t, void *d_out, void *stream)
+{
+    if (check_gen(g)) return RNG_EINVAL;
+    if (t != RNG_U32 && t != RNG_F32) return fail(RNG_EINVAL, "unknown dtype %d", t);
+    Shape s = tuned_shape(g, t);
+    return rng_generate_ex(g, d_state, n_streams, n, t, d_out, s.wg, s.unroll, stream);
+}
+
+int rng_skip(int g, uint32_t *d_state, uint64_t n_streams, uint64_t k, void *stream)
+{
+    if (check_gen(g)) return RNG_EINVAL;
+    if (n_streams == 0 || k == 0) return RNG_OK;
+    if (!d_state) return fail(RNG_EINVAL, "d_state is NULL");
+    if ((uintptr_t)d_state & 3) return fail(RNG_EINVAL, "d_state not 4-byte aligned");
+    if (int rc = check_sizes(n_streams, 1, gen_words(g))) return rc;
+    DevTables tab;
+    if (int rc = device_tables(&tab)) return rc;
+    return check_launch(dispatch_skip(g, d_state, n_streams, k, tab, (hipStream_t)stream), "rng_skip");
+}
+
+int rng_split_workspace_bytes(int g, uint64_t n_threads, uint64_t *bytes)
+{
+    if (check_gen(g)) return RNG_EINVAL;
+    if (!bytes) return fail(RNG_EINVAL, "bytes is NULL");
+    uint64_t b;
+    if (mul_overflows(n_threads, (uint64_t)gen_words(g) * 4, &b)) return fail(RNG_ERANGE, "n_threads too large");
+    *bytes = b;
+    return RNG_OK;
+}
+
+int rng_generate_split(int g, const uint32_t *d_state_one, uint64_t total, uint64_t n_threads, int t,
+                       void *d_out, uint32_t *d_final_state, void *d_workspace, uint64_t workspace_bytes,
+                       void *stream)
+{
+    if (check_gen(g)) return RNG_EINVAL;
+    if (t != RNG_U32 && t != RNG_F32) return fail(RNG_EINVAL, "unknown dtype %d", t);
+    if (!d_state_one || !d_final_state) return fail(RNG_EINVAL, "NULL state");
+    if (total == 0) {
+        // nothing generated: the final state is the initial one
+        if (d_final_state == d_state_one) return RNG_OK;
+        hipError_t e = hipMemcpyAsync(d_final_state, d_state_one, gen_words(g) * 4, hipMemcpyDeviceToDevice,
+                                      (hipStream_t)stream);
+        return e == hipSuccess ? RNG_OK : hip_fail(e, "hipMemcpyAsync");
+    }
+    if (!d_out || !d_workspace) return fail(RNG_EINVAL, "NULL output or workspace");
+    if (n_threads == 0) return fail(RNG_EINVAL, "n_threads is 0");
+    if (((uintptr_t)d_out & 3) || ((uintptr_t)d_workspace & 255) || ((uintptr_t)d_state_one & 3) ||
+        ((uintptr_t)d_final_state & 3))
+        return fail(RNG_EINVAL, "misaligned pointer");
+    if (int rc = check_sizes(1, total, 1)) return rc;
+    const int W = gen_words(g);
+    const uint64_t C = (total + n_threads - 1) / n_threads;
+    const uint64_t T = (total + C - 1) / C;  // threads with work
+    uint64_t need;
+    rng_split_workspace_bytes(g, T, &need);
+    if (workspace_bytes < need)
+        return fail(RNG_ENOMEM, "workspace %llu bytes < %llu", (unsigned long long)workspace_bytes,
+                    (unsigned long long)need);
+    DevTables tab;
+    if (int rc = device_tables(&tab)) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t *ws = (uint32_t *)d_workspace;
+    int rc = check_launch(dispatch_state_copy(g, d_state_one, 1, 0, ws, T, 0, st), "split: init");
+    if (rc) return rc;
+    for (uint64_t lo = 1; lo < T; lo *= 2) {
+        uint64_t dist;
+        if (mul_overflows(C, lo, &dist)) return fail(RNG_ERANGE, "jump distance overflows");
+        rc = check_launch(dispatch_tree_level(g, ws, T, lo, dist, tab, st), "split: tree level");
+        if (rc) return rc;
+    }
+    const uint64_t rem = total - (T - 1) * C;  // samples of the last thread
+    const uint64_t full = rem == C ? T : T - 1;
+    Shape shape = tuned_shape(g, t);
+    if (full) {
+        rc = generate_impl(g, t, ws, T, full, C, d_out, shape, true, st);
+        if (rc) return rc;
+    }
+    if (full < T) {
+        rc = generate_impl(g, t, ws + (T - 1), T, 1, rem, (uint32_t *)d_out + (T - 1) * C, shape, true, st);
+        if (rc) return rc;
+    }
+    (void)W;
+    return check_launch(dispatch_state_copy(g, ws, T, T - 1, d_final_state, 1, 0, st), "split: final");
+}
+
+int rng_fused_pi(int g, uint32_t *d_state, uint64_t n_streams, uint64_t n, uint64_t *d_count, void *stream)
+{
+    if (check_gen(g)) return RNG_EINVAL;
+    if (n_streams == 0 || n == 0) return RNG_OK;
+    if (!d_state || !d_count) return fail(RNG_EINVAL, "NULL state or count");
+    if (((uintptr_t)d_state & 3) || ((uintptr_t)d_count & 7)) return fail(RNG_EINVAL, "misaligned pointer");
+    if (int rc = check_sizes(n_streams, n, gen_words(g))) return rc;
+    DevTables tab;
+    if (int rc = device_tables(&tab)) return rc;
+    FusedArgs a{};
+    a.state = d_state;
+    a.ld = n_streams;
+    a.S = n_streams;
+    a.N = n;
+    a.count = d_count;
+    a.tab = tab;
+    choose_chunks(g, n_streams, n, 8, &a.C, &a.P);
+    if (a.P == 1) a.C = n;
+    return check_launch(dispatch_fused(g, a, (hipStream_t)stream), "rng_fused_pi");
+}
+
+}  // extern "C"

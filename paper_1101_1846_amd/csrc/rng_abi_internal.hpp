@@ -1,0 +1,34 @@
+// rng_abi_internal.hpp -- helpers shared by the C ABI translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rng_internal.hpp"
+
+namespace rngx {
+
+struct Shape {
+    uint32_t wg, unroll;
+};
+
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+int check_launch(int rc, const char *what);
+int check_gen(int g);
+int check_sizes(uint64_t S, uint64_t N, uint64_t words);
+int device_tables(DevTables *out);
+int gen_words(int g);
+bool valid_shape(uint32_t wg, uint32_t unroll);
+Shape tuned_shape(int g, int dt);
+void set_tuned_shape(int g, int dt, Shape s);
+void choose_chunks(int g, uint64_t S, uint64_t N, uint64_t align, uint64_t *C, uint32_t *P);
+int generate_impl(int g, int dt, uint32_t *d_state, uint64_t ld, uint64_t S, uint64_t N, void *d_out,
+                  Shape shape, bool staged, hipStream_t st);
+int dispatch_generate(int g, int dt, const GenArgs &a, int wg, int unroll, bool staged, hipStream_t st);
+int dispatch_skip(int g, uint32_t *st, uint64_t S, uint64_t k, const DevTables &tab, hipStream_t s);
+int dispatch_tree_level(int g, uint32_t *ws, uint64_t T, uint64_t lo, uint64_t dist, const DevTables &tab,
+                        hipStream_t s);
+int dispatch_state_copy(int g, const uint32_t *src, uint64_t ss, uint64_t si, uint32_t *dst, uint64_t ds,
+                        uint64_t di, hipStream_t s);
+
+}  // namespace rngx

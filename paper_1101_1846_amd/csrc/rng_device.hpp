@@ -1,0 +1,373 @@
+// rng_device.hpp -- HIP device functions for the generators of Hissoiny,
+// Despres & Ozell (arXiv:1101.1846): state load/store, one step, seeding,
+// jump-ahead and the FP32 map.  The library's kernels are built from these,
+// and another kernel can include this header to draw numbers inline (the
+// "on the fly" use the paper discusses in Sec. III.A.2 and III.B).
+//
+// Each generator is a small struct whose state lives in VGPRs:
+//   load(state, S, s) / store(state, S, s)  structure-of-arrays [W][S]
+//   next()                                   step, then emit (eq. (1))
+//   jump(k, tab)                             advance by k steps
+//   seed(d, tab)                             state from SplitMix64 draws d[]
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rngx {
+
+// Device copies of the host tables (host_math.hpp), one set per device.
+struct DevTables {
+    const uint16_t *t392;          // [392] base-2^16 multipliers, ascending
+    const uint64_t *mwc32_pow;     // [64] a^(2^b) * 2^64 mod m
+    const uint32_t *lcg_pow;       // [64][2] (A, C) of 2^b LCG steps
+    const uint32_t *xs32_pow;      // [64][32] columns of M^(2^b)
+    const uint32_t *mwc16_pow;     // [392][64] a_i^(2^b) * 2^48 mod m_i
+    const uint32_t *xs256_pow;     // [64][256][8] columns of M^(2^b)
+    uint32_t mwc32_a;              // 65274
+    uint64_t mwc32_m;              // a * 2^32 - 1
+};
+
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+// SplitMix64 output number n of a generator started at `seed`
+// (Steele, Lea & Flood 2014): mix(seed + (n+1) * gamma).
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t n)
+{
+    uint64_t z = seed + (n + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// The exact FP32 uniform: top 24 bits times 2^-24.
+__device__ __forceinline__ float to_unit_f32(uint32_t u)
+{
+    return (float)(u >> 8) * 0x1p-24f;
+}
+
+// ---------------------------------------------------------------- MWC algebra
+// For base b = 2^w and m = a*b - 1 we have a*b = 1 (mod m), so for any X,
+// fold(X) = (X >> w) + a * (X mod b) is congruent to a*X.  A product z*A is
+// reduced with a constant stored pre-multiplied by b^(-f) = a^f (f folds):
+// a^f * (z * A * b^f) = z*A (mod m).  The bounds below keep every fold exact.
+
+// m = a*2^32 - 1 < 2^48; z in [1, m-1]; Af = A * 2^64 mod m.  Two folds.
+__device__ __forceinline__ uint64_t mwc32_mulmod(uint64_t z, uint64_t Af, uint32_t a, uint64_t m)
+{
+    uint32_t zl = (uint32_t)z, zh = (uint32_t)(z >> 32);
+    uint32_t fl = (uint32_t)Af, fh = (uint32_t)(Af >> 32);
+    uint64_t t0 = (uint64_t)zl * fl;
+    // P = z*Af < m^2 < 0.993 * 2^96; P_hi = P >> 32 < 0.993 * 2^64
+    uint64_t phi = (t0 >> 32) + (uint64_t)zl * fh + (uint64_t)zh * fl + ((uint64_t)(zh * fh) << 32);
+    uint64_t y1 = phi + (uint64_t)a * (uint32_t)t0;         // < 2^64
+    uint64_t y2 = (y1 >> 32) + (uint64_t)a * (uint32_t)y1;  // < m + 2^32 < 2m
+    return y2 >= m ? y2 - m : y2;
+}
+
+// m = a*2^16 - 1 < 2^32; z in [1, m-1]; Af = A * 2^48 mod m.  Three folds.
+__device__ __forceinline__ uint32_t mwc16_mulmod(uint32_t z, uint32_t Af, uint32_t a)
+{
+    uint32_t m = a * 65536u - 1u;
+    uint64_t p = (uint64_t)z * Af;                               // < 2^64
+    uint64_t y1 = (p >> 16) + (uint64_t)a * (uint32_t)(p & 0xFFFFu);   // < 2^48 + 2^32
+    uint64_t y2 = (y1 >> 16) + (uint64_t)a * (uint32_t)(y1 & 0xFFFFu); // < 2^32 + 2^16 (a+1)
+    uint32_t y3 = (uint32_t)(y2 >> 16) + a * (uint32_t)(y2 & 0xFFFFu);  // < m + 2^16 + 3 < 2m
+    return y3 >= m ? y3 - m : y3;
+}
+
+// Index of multiplier a in the ascending table (binary search).
+__device__ __forceinline__ uint32_t t392_index(const uint16_t *t, uint32_t a)
+{
+    uint32_t lo = 0, hi = 392;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (t[mid] <= a) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// MWC16 word from 16+16 seed bits with c < a and z outside {0, a*2^16 - 1}.
+__device__ __forceinline__ uint32_t mwc16_seed_word(uint32_t h, uint32_t a)
+{
+    uint32_t z = ((h >> 16) % a) << 16 | (h & 0xFFFFu);
+    uint32_t m = a * 65536u - 1u;
+    z = z == 0 ? 1u : z;
+    return z == m ? m - 1u : z;
+}
+
+__device__ __forceinline__ void mwc16_pair(uint64_t d, const uint16_t *t, uint32_t &a1, uint32_t &a2)
+{
+    uint32_t i = (uint32_t)d % 392u;
+    uint32_t j = (i + 1u + (uint32_t)(d >> 32) % 391u) % 392u;
+    a1 = t[i];
+    a2 = t[j];
+}
+
+// ---------------------------------------------------------------- GF(2)
+// y <- M y for a 32x32 bit matrix given by its 32 columns.
+__device__ __forceinline__ uint32_t gf2_apply32(const uint32_t *__restrict__ col, uint32_t y)
+{
+    uint32_t r = 0;
+#pragma unroll
+    for (int b = 0; b < 32; ++b) {
+        uint32_t mask = (uint32_t)__builtin_amdgcn_sbfe((int)y, b, 1);
+        r ^= col[b] & mask;
+    }
+    return r;
+}
+
+// v <- M v for the 256x256 matrix of the r = 8 XorShift, 256 columns of 8
+// words.  Every lane of a wave reads the same column, so the matrix streams
+// through the scalar cache.  Kept out of line: one copy serves every kernel
+// that jumps.
+struct V8 {
+    uint32_t v[8];
+};
+
+__device__ __noinline__ V8 gf2_apply256(const uint32_t *__restrict__ col, V8 in)
+{
+    V8 r = {{0, 0, 0, 0, 0, 0, 0, 0}};
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+#pragma unroll
+        for (int b = 0; b < 32; ++b) {
+            uint32_t mask = (uint32_t)__builtin_amdgcn_sbfe((int)in.v[w], b, 1);
+            const uint32_t *c = col + (32 * w + b) * 8;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) r.v[i] ^= c[i] & mask;
+        }
+    }
+    return r;
+}
+
+// ---------------------------------------------------------------- generators
+enum { G_MWC32 = 1, G_XS256 = 2, G_XS32 = 3, G_KISS = 4, G_MWC1616 = 5 };
+
+// Eq. (2)-(3), b = 2^32: t = a*x + c (one 32x32+32 -> 64 multiply-add).
+struct GenMWC32 {
+    static constexpr int kId = G_MWC32, W = 2, D = 1;
+    uint32_t x, c, a;
+    __device__ void load(const uint32_t *st, uint64_t S, uint64_t s, const DevTables &tab)
+    {
+        x = st[s];
+        c = st[S + s];
+        a = tab.mwc32_a;
+    }
+    __device__ void store(uint32_t *st, uint64_t S, uint64_t s) const
+    {
+        st[s] = x;
+        st[S + s] = c;
+    }
+    __device__ __forceinline__ uint32_t next()
+    {
+        uint64_t t = (uint64_t)a * x + c;
+        x = (uint32_t)t;
+        c = (uint32_t)(t >> 32);
+        return x;
+    }
+    __device__ void jump(uint64_t k, const DevTables &tab)
+    {
+        uint64_t z = (uint64_t)c << 32 | x;
+        for (int b = 0; b < 64 && (k >> b); ++b)
+            if ((k >> b) & 1) z = mwc32_mulmod(z, tab.mwc32_pow[b], tab.mwc32_a, tab.mwc32_m);
+        x = (uint32_t)z;
+        c = (uint32_t)(z >> 32);
+    }
+    __device__ void seed(const uint64_t *d, const DevTables &tab)
+    {
+        a = tab.mwc32_a;
+        uint64_t z = (uint64_t)((uint32_t)(d[0] >> 32) % a) << 32 | (uint32_t)d[0];
+        z = z == 0 ? 1 : z;
+        z = z == tab.mwc32_m ? tab.mwc32_m - 1 : z;
+        x = (uint32_t)z;
+        c = (uint32_t)(z >> 32);
+    }
+};
+
+// Eq. (5): window v[0..7] = (v_{n-8} .. v_{n-1}).  14 VALU operations per
+// number on gfx950 (7 shifts, 2 two-input and 5 three-input xors) against
+// the paper's 18 two-input operations.
+struct GenXS256 {
+    static constexpr int kId = G_XS256, W = 8, D = 4;
+    uint32_t v[8];
+    __device__ void load(const uint32_t *st, uint64_t S, uint64_t s, const DevTables &)
+    {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = st[i * S + s];
+    }
+    __device__ void store(uint32_t *st, uint64_t S, uint64_t s) const
+    {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) st[i * S + s] = v[i];
+    }
+    __device__ __forceinline__ uint32_t next()
+    {
+        uint32_t u1 = v[7] ^ (v[7] << 13);   // (I+L^13) v_{n-1}
+        uint32_t u8 = v[0] ^ (v[0] >> 7);    // (I+R^7) v_{n-8}
+        uint32_t p = xor3(u1, u1 << 9, v[4]);              // (I+L^9)(.) + v_{n-4}
+        uint32_t q = xor3(v[4] << 7, v[3], v[3] >> 3);      // L^7 v_{n-4} + (I+R^3) v_{n-5}
+        uint32_t r = xor3(v[1], v[1] >> 10, u8);            // (I+R^10) v_{n-7} + u8
+        uint32_t vn = xor3(p, q, r) ^ (u8 << 24);           // + L^24 u8
+#pragma unroll
+        for (int i = 0; i < 7; ++i) v[i] = v[i + 1];
+        v[7] = vn;
+        return vn;
+    }
+    __device__ void jump(uint64_t k, const DevTables &tab)
+    {
+        V8 x;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) x.v[i] = v[i];
+        for (int b = 0; b < 64 && (k >> b); ++b)
+            if ((k >> b) & 1) x = gf2_apply256(tab.xs256_pow + (size_t)b * 2048, x);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = x.v[i];
+    }
+    __device__ void seed(const uint64_t *d, const DevTables &)
+    {
+        uint32_t any = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            v[2 * i] = (uint32_t)d[i];
+            v[2 * i + 1] = (uint32_t)(d[i] >> 32);
+            any |= v[2 * i] | v[2 * i + 1];
+        }
+        if (!any) v[7] = 1;
+    }
+};
+
+// Eq. (6): y ^= y<<13; y ^= y>>17; y ^= y<<5.
+struct GenXS32 {
+    static constexpr int kId = G_XS32, W = 1, D = 1;
+    uint32_t y;
+    __device__ void load(const uint32_t *st, uint64_t, uint64_t s, const DevTables &) { y = st[s]; }
+    __device__ void store(uint32_t *st, uint64_t, uint64_t s) const { st[s] = y; }
+    __device__ __forceinline__ uint32_t next()
+    {
+        y ^= y << 13;
+        y ^= y >> 17;
+        y ^= y << 5;
+        return y;
+    }
+    __device__ void jump(uint64_t k, const DevTables &tab)
+    {
+        for (int b = 0; b < 64 && (k >> b); ++b)
+            if ((k >> b) & 1) y = gf2_apply32(tab.xs32_pow + b * 32, y);
+    }
+    __device__ void seed(const uint64_t *d, const DevTables &)
+    {
+        y = (uint32_t)d[0];
+        y = y ? y : 1u;
+    }
+};
+
+// One base-2^16 MWC word z = c*2^16 + x: z <- a*(z & 0xFFFF) + (z >> 16)
+// (eq. (2)-(3) with the mask and shift of Sec. II.A.1).  Both factors are
+// below 2^16, so the 24-bit multiply(-add) is exact.
+__device__ __forceinline__ uint32_t mwc16_step(uint32_t z, uint32_t a)
+{
+    return __umul24(a, z & 0xFFFFu) + (z >> 16);
+}
+
+// Sec. III.A.1: the paper's MWC, two base-2^16 words with distinct
+// multipliers, output (z << 16) + w.
+struct GenMWC1616 {
+    static constexpr int kId = G_MWC1616, W = 4, D = 2;
+    uint32_t z, w, a1, a2;
+    __device__ void load(const uint32_t *st, uint64_t S, uint64_t s, const DevTables &)
+    {
+        z = st[s];
+        w = st[S + s];
+        a1 = st[2 * S + s];
+        a2 = st[3 * S + s];
+    }
+    __device__ void store(uint32_t *st, uint64_t S, uint64_t s) const
+    {
+        st[s] = z;
+        st[S + s] = w;
+        st[2 * S + s] = a1;
+        st[3 * S + s] = a2;
+    }
+    __device__ __forceinline__ uint32_t next()
+    {
+        z = mwc16_step(z, a1);
+        w = mwc16_step(w, a2);
+        return (z << 16) + w;
+    }
+    __device__ void jump(uint64_t k, const DevTables &tab)
+    {
+        const uint32_t *p1 = tab.mwc16_pow + t392_index(tab.t392, a1) * 64;
+        const uint32_t *p2 = tab.mwc16_pow + t392_index(tab.t392, a2) * 64;
+        for (int b = 0; b < 64 && (k >> b); ++b)
+            if ((k >> b) & 1) {
+                z = mwc16_mulmod(z, p1[b], a1);
+                w = mwc16_mulmod(w, p2[b], a2);
+            }
+    }
+    __device__ void seed(const uint64_t *d, const DevTables &tab)
+    {
+        mwc16_pair(d[0], tab.t392, a1, a2);
+        z = mwc16_seed_word((uint32_t)d[1], a1);
+        w = mwc16_seed_word((uint32_t)(d[1] >> 32), a2);
+    }
+};
+
+// Sec. II.A.3 / III.A.3: KISS = (MWC1616 xor LCG) + XS32, LCG of eq. (7).
+struct GenKISS {
+    static constexpr int kId = G_KISS, W = 6, D = 3;
+    uint32_t z, w, jsr, jcong, a1, a2;
+    __device__ void load(const uint32_t *st, uint64_t S, uint64_t s, const DevTables &)
+    {
+        z = st[s];
+        w = st[S + s];
+        jsr = st[2 * S + s];
+        jcong = st[3 * S + s];
+        a1 = st[4 * S + s];
+        a2 = st[5 * S + s];
+    }
+    __device__ void store(uint32_t *st, uint64_t S, uint64_t s) const
+    {
+        st[s] = z;
+        st[S + s] = w;
+        st[2 * S + s] = jsr;
+        st[3 * S + s] = jcong;
+        st[4 * S + s] = a1;
+        st[5 * S + s] = a2;
+    }
+    __device__ __forceinline__ uint32_t next()
+    {
+        z = mwc16_step(z, a1);
+        w = mwc16_step(w, a2);
+        jcong = 69069u * jcong + 1234567u;
+        jsr ^= jsr << 13;
+        jsr ^= jsr >> 17;
+        jsr ^= jsr << 5;
+        return (((z << 16) + w) ^ jcong) + jsr;
+    }
+    __device__ void jump(uint64_t k, const DevTables &tab)
+    {
+        const uint32_t *p1 = tab.mwc16_pow + t392_index(tab.t392, a1) * 64;
+        const uint32_t *p2 = tab.mwc16_pow + t392_index(tab.t392, a2) * 64;
+        for (int b = 0; b < 64 && (k >> b); ++b)
+            if ((k >> b) & 1) {
+                z = mwc16_mulmod(z, p1[b], a1);
+                w = mwc16_mulmod(w, p2[b], a2);
+                jsr = gf2_apply32(tab.xs32_pow + b * 32, jsr);
+                jcong = tab.lcg_pow[2 * b] * jcong + tab.lcg_pow[2 * b + 1];
+            }
+    }
+    __device__ void seed(const uint64_t *d, const DevTables &tab)
+    {
+        mwc16_pair(d[0], tab.t392, a1, a2);
+        z = mwc16_seed_word((uint32_t)d[1], a1);
+        w = mwc16_seed_word((uint32_t)(d[1] >> 32), a2);
+        jsr = (uint32_t)d[2];
+        jsr = jsr ? jsr : 1u;
+        jcong = (uint32_t)(d[2] >> 32);
+    }
+};
+
+}  // namespace rngx

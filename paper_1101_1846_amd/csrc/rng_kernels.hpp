@@ -1,0 +1,364 @@
+// rng_kernels.hpp -- kernel templates and their launchers.  Each generator's
+// translation unit (gen_*.hip) includes this file and instantiates the
+// launchers for its generator only, so the five units compile in parallel.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rng_device.hpp"
+#include "rng_internal.hpp"
+
+namespace rngx {
+
+// Compiler-only ordering point between the LDS writes of a tile and the LDS
+// reads of the transposed store (and the next tile's writes).  A wavefront's
+// LDS instructions execute in issue order, so no hardware wait is needed.
+#define RNGX_COMPILER_FENCE() asm volatile("" ::: "memory")
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <int DT>
+__device__ __forceinline__ uint32_t out_bits(uint32_t u)
+{
+    if constexpr (DT == RNG_DT_F32) return __float_as_uint(to_unit_f32(u));
+    else return u;
+}
+
+// ------------------------------------------------------------------ seeding
+template <class G>
+__global__ __launch_bounds__(256) void k_seed(uint32_t *__restrict__ st, uint64_t S, uint64_t seed,
+                                              uint64_t first, DevTables tab)
+{
+    uint64_t s = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= S) return;
+    uint64_t d[4];
+#pragma unroll
+    for (int j = 0; j < G::D; ++j) d[j] = splitmix64_at(seed, (first + s) * G::D + j);
+    G g;
+    g.seed(d, tab);
+    g.store(st, S, s);
+}
+
+// ------------------------------------------------------------------ skip
+template <class G>
+__global__ __launch_bounds__(256) void k_skip(uint32_t *__restrict__ st, uint64_t S, uint64_t k,
+                                              DevTables tab)
+{
+    uint64_t s = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= S) return;
+    G g;
+    g.load(st, S, s, tab);
+    g.jump(k, tab);
+    g.store(st, S, s);
+}
+
+// One level of the doubling tree used by sequence splitting: thread t in
+// [lo, min(2 lo, T)) starts where thread t - lo starts plus dist samples.
+template <class G>
+__global__ __launch_bounds__(256) void k_tree_level(uint32_t *__restrict__ ws, uint64_t T, uint64_t lo,
+                                                    uint64_t dist, DevTables tab)
+{
+    uint64_t t = lo + (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= T || t >= 2 * lo) return;
+    G g;
+    g.load(ws, T, t - lo, tab);
+    g.jump(dist, tab);
+    g.store(ws, T, t);
+}
+
+// ------------------------------------------------------------------ generate
+// Lane mapping: wave w serves streams [64 sb, 64 sb + 64) for chunk j, with
+// sb = w / P and j = w % P.  Chunk j covers samples [j C, min((j+1) C, N)) of
+// each of its streams and starts from the stream state jumped by j C (the
+// jump distance is uniform across the wave).  The last chunk writes the
+// state back.
+//
+// Store path (kStaged): each lane produces K consecutive samples of its own
+// stream into a wave-private LDS tile [64][K + 4]; the wave then writes the
+// tile row by row so that consecutive lanes store consecutive addresses of
+// one stream (dwordx4 when rows are 16-byte aligned), instead of 64 lanes
+// each touching a different row.  Without kStaged every lane stores its own
+// row directly from registers.
+template <class G, int DT, int WG, int U, int K, bool kStaged>
+__global__ __launch_bounds__(WG) void k_generate(GenArgs a)
+{
+    static_assert(K % U == 0 && K % 4 == 0, "tile depth");
+    constexpr int LD = K + 4;
+    constexpr int NW = WG / 64;
+    __shared__ __attribute__((aligned(16))) uint32_t lds[kStaged ? NW * 64 * LD : 1];
+
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t wave = (uint64_t)blockIdx.x * NW + wv;
+    const uint64_t sb = wave / a.P, j = wave - sb * a.P;
+    const uint64_t s0 = sb * 64;
+    if (s0 >= a.S) return;
+    const uint64_t kb = j * a.C;
+    if (kb >= a.N) return;
+    const uint64_t ke = min(kb + a.C, a.N);
+    const uint32_t rows = (uint32_t)min<uint64_t>(64, a.S - s0);
+    const bool valid = (uint32_t)lane < rows;
+    const uint64_t s = valid ? s0 + lane : s0;
+
+    G g;
+    g.load(a.state, a.ld, s, a.tab);
+    if (j) g.jump(kb, a.tab);
+
+    uint32_t *tile = kStaged ? &lds[wv * 64 * LD] : nullptr;
+    uint32_t *out = (uint32_t *)a.out;
+    const uint64_t N = a.N;
+
+    for (uint64_t k0 = kb; k0 < ke; k0 += K) {
+        const uint32_t cnt = (uint32_t)min<uint64_t>(K, ke - k0);
+        if constexpr (kStaged) {
+            uint32_t *row = tile + lane * LD;
+            if (cnt == K) {
+#pragma unroll 1
+                for (int k = 0; k < K; k += U) {
+                    uint32_t v[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) v[u] = out_bits<DT>(g.next());
+                    if constexpr (U % 4 == 0) {
+#pragma unroll
+                        for (int u = 0; u < U; u += 4)
+                            *(uint4 *)&row[k + u] = make_uint4(v[u], v[u + 1], v[u + 2], v[u + 3]);
+                    } else if constexpr (U == 2) {
+                        *(uint2 *)&row[k] = make_uint2(v[0], v[1]);
+                    } else {
+                        row[k] = v[0];
+                    }
+                }
+            } else {
+                for (uint32_t k = 0; k < cnt; ++k) row[k] = out_bits<DT>(g.next());
+            }
+            RNGX_COMPILER_FENCE();
+            if (a.vec4) {
+                constexpr int QPR = K / 4;  // 16-byte quads per row
+#pragma unroll
+                for (int i = 0; i < QPR; ++i) {
+                    const int f = i * 64 + lane, r = f / QPR, q = f % QPR;
+                    if ((uint32_t)r < rows && (uint32_t)(4 * q) < cnt) {
+                        u32x4 val = *(const u32x4 *)&tile[r * LD + 4 * q];
+                        u32x4 *dst = (u32x4 *)(out + (s0 + r) * N + k0 + 4 * q);
+                        if (a.nt) __builtin_nontemporal_store(val, dst);
+                        else *dst = val;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < K; ++i) {
+                    const int f = i * 64 + lane, r = f / K, c = f % K;
+                    if ((uint32_t)r < rows && (uint32_t)c < cnt) {
+                        uint32_t val = tile[r * LD + c];
+                        uint32_t *dst = out + (s0 + r) * N + k0 + c;
+                        if (a.nt) __builtin_nontemporal_store(val, dst);
+                        else *dst = val;
+                    }
+                }
+            }
+            RNGX_COMPILER_FENCE();
+        } else {
+            uint32_t *dst = out + s * N + k0;
+            if (cnt == K) {
+#pragma unroll 1
+                for (int k = 0; k < K; k += U) {
+                    uint32_t v[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) v[u] = out_bits<DT>(g.next());
+                    if (valid) {
+                        bool done = false;
+                        if constexpr (U % 4 == 0) {
+                            if (a.vec4) {
+#pragma unroll
+                                for (int u = 0; u < U; u += 4)
+                                    *(uint4 *)&dst[k + u] = make_uint4(v[u], v[u + 1], v[u + 2], v[u + 3]);
+                                done = true;
+                            }
+                        }
+                        if (!done) {
+#pragma unroll
+                            for (int u = 0; u < U; ++u) dst[k + u] = v[u];
+                        }
+                    }
+                }
+            } else {
+                for (uint32_t k = 0; k < cnt; ++k) {
+                    uint32_t v = out_bits<DT>(g.next());
+                    if (valid) dst[k] = v;
+                }
+            }
+        }
+    }
+    if (valid && ke == a.N) g.store(a.state, a.ld, s);
+}
+
+// ------------------------------------------------------------------ fused pi
+// Pairs (u_{2k}, u_{2k+1}) -> i = u >> 8, j = u >> 8; count i^2 + j^2 < 2^48
+// with 24-bit multiplies: i^2 = hi * 2^32 + lo, hi < 2^16.  Chunk lengths are
+// even so that pairs never straddle chunks.
+template <class G, int WG, int U>
+__global__ __launch_bounds__(WG) void k_fused_pi(FusedArgs a)
+{
+    static_assert(U % 2 == 0, "pairs");
+    constexpr int NW = WG / 64;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t wave = (uint64_t)blockIdx.x * NW + wv;
+    const uint64_t sb = wave / a.P, j = wave - sb * a.P;
+    const uint64_t s0 = sb * 64;
+    if (s0 >= a.S) return;
+    const uint64_t kb = j * a.C;
+    if (kb >= a.N) return;
+    const uint64_t ke = min(kb + a.C, a.N);
+    const uint32_t rows = (uint32_t)min<uint64_t>(64, a.S - s0);
+    const bool valid = (uint32_t)lane < rows;
+    const uint64_t s = valid ? s0 + lane : s0;
+
+    G g;
+    g.load(a.state, a.ld, s, a.tab);
+    if (j) g.jump(kb, a.tab);
+
+    const uint64_t n = ke - kb;
+    const uint64_t full = n / U;
+    uint64_t total = 0;
+    uint32_t cnt = 0;
+    for (uint64_t it = 0; it < full; ++it) {
+#pragma unroll
+        for (int u = 0; u < U; u += 2) {
+            uint32_t x = g.next() >> 8, y = g.next() >> 8;
+            uint64_t px = (uint64_t)x * x, py = (uint64_t)y * y;  // 24 x 24 -> 48 bits
+            uint32_t xl = (uint32_t)px, xh = (uint32_t)(px >> 32);
+            uint32_t yl = (uint32_t)py, yh = (uint32_t)(py >> 32);
+            uint32_t lo = xl + yl;
+            uint32_t hi = xh + yh + (lo < xl);
+            cnt += hi < 65536u;
+        }
+        if ((it & 0xFFFF) == 0xFFFF) { total += cnt; cnt = 0; }
+    }
+    for (uint64_t r = full * U; r + 1 < n; r += 2) {
+        uint32_t x = g.next() >> 8, y = g.next() >> 8;
+        uint64_t q = (uint64_t)x * x + (uint64_t)y * y;
+        cnt += (q >> 48) == 0;
+    }
+    if (n & 1) g.next();
+    total += cnt;
+    if (!valid) total = 0;
+    // wave reduction, one 64-bit atomic per wave
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) total += __shfl_xor(total, off, 64);
+    if (lane == 0 && total) atomicAdd((unsigned long long *)a.count, (unsigned long long)total);
+    if (valid && ke == a.N) g.store(a.state, a.ld, s);
+}
+
+// ------------------------------------------------------------------ helpers
+// Copy one stream's state between a [W] contiguous buffer and slot `idx` of
+// a [W][T] structure-of-arrays buffer.
+template <int W>
+__global__ void k_state_copy(const uint32_t *__restrict__ src, uint64_t src_stride, uint64_t src_idx,
+                             uint32_t *__restrict__ dst, uint64_t dst_stride, uint64_t dst_idx)
+{
+    int w = threadIdx.x;
+    if (w < W) dst[w * dst_stride + dst_idx] = src[w * src_stride + src_idx];
+}
+
+// ------------------------------------------------------------------ launchers
+inline unsigned grid_for(uint64_t lanes, int wg) { return (unsigned)((lanes + wg - 1) / wg); }
+
+template <class G>
+int launch_seed_t(uint64_t seed, uint64_t first, uint64_t S, uint32_t *st, const DevTables &tab,
+                  hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_seed<G>, dim3(grid_for(S, 256)), dim3(256), 0, stream, st, S, seed, first, tab);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <class G>
+int launch_skip_t(uint32_t *st, uint64_t S, uint64_t k, const DevTables &tab, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_skip<G>, dim3(grid_for(S, 256)), dim3(256), 0, stream, st, S, k, tab);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <class G>
+int launch_tree_level_t(uint32_t *ws, uint64_t T, uint64_t lo, uint64_t dist, const DevTables &tab,
+                        hipStream_t stream)
+{
+    uint64_t n = min(lo, T - lo);
+    hipLaunchKernelGGL(k_tree_level<G>, dim3(grid_for(n, 256)), dim3(256), 0, stream, ws, T, lo, dist, tab);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <class G>
+int launch_state_copy_t(const uint32_t *src, uint64_t ss, uint64_t si, uint32_t *dst, uint64_t ds,
+                        uint64_t di, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_state_copy<G::W>, dim3(1), dim3(64), 0, stream, src, ss, si, dst, ds, di);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <class G, int DT, int WG, int U, bool kStaged>
+int launch_generate_shape(const GenArgs &a, hipStream_t stream)
+{
+    uint64_t waves = ((a.S + 63) / 64) * a.P;
+    uint64_t blocks = (waves + WG / 64 - 1) / (WG / 64);
+    hipLaunchKernelGGL((k_generate<G, DT, WG, U, kGenTile, kStaged>), dim3((unsigned)blocks), dim3(WG), 0,
+                       stream, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <class G, int DT, int WG>
+int launch_generate_u(const GenArgs &a, int unroll, bool staged, hipStream_t stream)
+{
+    if (!staged) return launch_generate_shape<G, DT, WG, 8, false>(a, stream);
+    switch (unroll) {
+    case 1: return launch_generate_shape<G, DT, WG, 1, true>(a, stream);
+    case 2: return launch_generate_shape<G, DT, WG, 2, true>(a, stream);
+    case 4: return launch_generate_shape<G, DT, WG, 4, true>(a, stream);
+    case 8: return launch_generate_shape<G, DT, WG, 8, true>(a, stream);
+    case 16: return launch_generate_shape<G, DT, WG, 16, true>(a, stream);
+    }
+    return -2;
+}
+
+template <class G, int DT>
+int launch_generate_wg(const GenArgs &a, int wg, int unroll, bool staged, hipStream_t stream)
+{
+    switch (wg) {
+    case 64: return launch_generate_u<G, DT, 64>(a, unroll, staged, stream);
+    case 128: return launch_generate_u<G, DT, 128>(a, unroll, staged, stream);
+    case 256: return launch_generate_u<G, DT, 256>(a, unroll, staged, stream);
+    case 512: return launch_generate_u<G, DT, 512>(a, unroll, staged, stream);
+    case 1024: return launch_generate_u<G, DT, 1024>(a, unroll, staged, stream);
+    }
+    return -2;
+}
+
+template <class G>
+int launch_generate_t(int dt, const GenArgs &a, int wg, int unroll, bool staged, hipStream_t stream)
+{
+    return dt == RNG_DT_F32 ? launch_generate_wg<G, RNG_DT_F32>(a, wg, unroll, staged, stream)
+                            : launch_generate_wg<G, RNG_DT_U32>(a, wg, unroll, staged, stream);
+}
+
+template <class G>
+int launch_fused_pi_t(const FusedArgs &a, hipStream_t stream)
+{
+    constexpr int WG = 256;
+    uint64_t waves = ((a.S + 63) / 64) * a.P;
+    uint64_t blocks = (waves + WG / 64 - 1) / (WG / 64);
+    hipLaunchKernelGGL((k_fused_pi<G, WG, 8>), dim3((unsigned)blocks), dim3(WG), 0, stream, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+#define RNGX_INSTANTIATE(G)                                                                            \
+    template int launch_seed_t<G>(uint64_t, uint64_t, uint64_t, uint32_t *, const DevTables &,        \
+                                  hipStream_t);                                                        \
+    template int launch_skip_t<G>(uint32_t *, uint64_t, uint64_t, const DevTables &, hipStream_t);    \
+    template int launch_tree_level_t<G>(uint32_t *, uint64_t, uint64_t, uint64_t, const DevTables &,  \
+                                        hipStream_t);                                                  \
+    template int launch_state_copy_t<G>(const uint32_t *, uint64_t, uint64_t, uint32_t *, uint64_t,  \
+                                        uint64_t, hipStream_t);                                        \
+    template int launch_generate_t<G>(int, const GenArgs &, int, int, bool, hipStream_t);             \
+    template int launch_fused_pi_t<G>(const FusedArgs &, hipStream_t);
+
+}  // namespace rngx

@@ -26,3 +26,12 @@ def oracle():
     import oracle as O
     O.lib()
     return O
+
+
+def pytest_collection_modifyitems(config, items):
+    if gpu_available():
+        return
+    skip = pytest.mark.skip(reason="no GPU visible (gpu tests run on an MI355X)")
+    for item in items:
+        if "gpu" in item.keywords:
+            item.add_marker(skip)

@@ -1,0 +1,122 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports
+every symbol the header declares, its host tables agree with the oracle, and
+argument validation returns the documented codes before touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+           if f.endswith(".h")]
+
+
+@pytest.fixture(scope="module")
+def rng():
+    import paper_1101_1846_amd as R
+    return R
+
+
+def declared_functions():
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(rng_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("rng_seed", "rng_generate", "rng_skip", "rng_generate_split", "rng_fused_pi"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(rng):
+    out = subprocess.run(["nm", "-D", "--defined-only", rng.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (rng_\w+)", out))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    for n in declared_functions():
+        assert hasattr(rng.raw(), n)
+
+
+def test_host_tables_match_oracle(rng, oracle):
+    """The library finds its multipliers with Miller-Rabin; the oracle with
+    trial division.  Both must give the paper's 392 and a = 65274."""
+    table, n = oracle.mwc16_table()
+    assert rng.rng_mwc16_multipliers() == table.tolist()
+    assert rng.rng_mwc32_multiplier() == oracle.mwc32_multiplier()
+
+
+def test_state_words(rng, oracle):
+    for name, g in rng.GENERATORS.items():
+        assert rng.rng_state_words(g) == oracle.state_words(oracle.GENERATORS[name])
+
+
+def test_strerror(rng):
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert rng.rng_strerror(code)
+    assert rng.rng_strerror(-99) == "unknown error"
+
+
+def test_argument_validation(rng):
+    L = rng.raw()
+    fake = 0x1000  # never dereferenced: every call below fails validation first
+    assert L.rng_generate(99, fake, 1, 1, 0, fake, None) == rng.RNG_EINVAL
+    assert L.rng_generate(rng.RNG_XS256, fake, 1, 1, 7, fake, None) == rng.RNG_EINVAL
+    assert L.rng_generate(rng.RNG_XS256, None, 1, 1, 0, fake, None) == rng.RNG_EINVAL
+    assert L.rng_generate(rng.RNG_XS256, fake, 1, 1, 0, None, None) == rng.RNG_EINVAL
+    assert L.rng_generate(rng.RNG_XS256, fake + 2, 1, 1, 0, fake, None) == rng.RNG_EINVAL
+    assert L.rng_generate(rng.RNG_XS256, fake, 1 << 40, 1 << 40, 0, fake, None) == rng.RNG_ERANGE
+    assert L.rng_generate_ex(rng.RNG_XS256, fake, 1, 1, 0, fake, 96, 8, None) == rng.RNG_EINVAL
+    assert L.rng_generate_ex(rng.RNG_XS256, fake, 1, 1, 0, fake, 256, 3, None) == rng.RNG_EINVAL
+    # empty work is a no-op that touches nothing
+    assert L.rng_generate(rng.RNG_KISS, None, 0, 5, 0, None, None) == rng.RNG_OK
+    assert L.rng_generate(rng.RNG_KISS, None, 5, 0, 0, None, None) == rng.RNG_OK
+    assert L.rng_seed(0, 1, 0, 4, fake, None) == rng.RNG_EINVAL
+    assert L.rng_seed(rng.RNG_MWC32, 1, 0, 4, None, None) == rng.RNG_EINVAL
+    assert L.rng_seed(rng.RNG_MWC32, 1, (1 << 64) - 2, 4, fake, None) == rng.RNG_ERANGE
+    assert L.rng_skip(rng.RNG_MWC32, None, 4, 5, None) == rng.RNG_EINVAL
+    assert L.rng_skip(rng.RNG_MWC32, None, 4, 0, None) == rng.RNG_OK
+    assert L.rng_fused_pi(rng.RNG_KISS, fake, 4, 4, fake + 4, None) == rng.RNG_EINVAL
+    assert L.rng_set_shape(rng.RNG_XS256, 0, 100, 8) == rng.RNG_EINVAL
+    assert L.rng_set_shape(rng.RNG_XS256, 2, 256, 8) == rng.RNG_EINVAL
+    assert "generator" in rng.rng_last_error() or rng.rng_last_error()
+
+
+def test_shape_roundtrip(rng):
+    g, t = rng.RNG_XS32, rng.RNG_F32
+    old = rng.rng_get_shape(g, t)
+    rng.rng_set_shape(g, t, 512, 4)
+    assert rng.rng_get_shape(g, t) == (512, 4)
+    rng.rng_set_shape(g, t, *old)
+
+
+def test_split_validation(rng):
+    L = rng.raw()
+    for name, g in rng.GENERATORS.items():
+        assert rng.rng_split_workspace_bytes(g, 1 << 20) == (1 << 20) * 4 * rng.rng_state_words(g)
+    fake = 0x10000
+    small = ctypes.c_uint64(8)
+    assert L.rng_generate_split(rng.RNG_XS256, fake, 1 << 20, 1 << 10, 0, fake, fake, fake, 16, None) \
+        == rng.RNG_ENOMEM
+    assert L.rng_generate_split(rng.RNG_XS256, fake, 100, 0, 0, fake, fake, fake, 1 << 20, None) \
+        == rng.RNG_EINVAL
+    assert L.rng_generate_split(rng.RNG_XS256, fake, 100, 4, 0, fake, fake, fake + 4, 1 << 20, None) \
+        == rng.RNG_EINVAL
+    del small
+
+
+def test_product_never_imports_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1101_1846_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".hpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "rng_oracle" not in text and "liboracle" not in text, f

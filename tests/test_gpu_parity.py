@@ -1,0 +1,172 @@
+"""Bit-exact parity of the HIP path (through the C ABI) with the serial CPU oracle.
+
+Sizes span several 64-lane waves and 32-sample LDS tiles with ragged tails, the
+chunked path (few streams, long rows), unaligned outputs, and every launch
+shape.  Full-size configurations live in test_gpu_configs.py.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+GENS = ["MWC32", "XS256", "XS32", "KISS", "MWC1616"]
+
+
+@pytest.fixture(scope="module")
+def rng():
+    import paper_1101_1846_amd as R
+    R.rng_init()
+    return R
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available()
+    return T
+
+
+def _dev_state(torch, rng, g, seed, S, first=0):
+    W = rng.rng_state_words(g)
+    st = torch.empty((W, S), dtype=torch.int32, device="cuda")
+    rng.rng_seed(g, seed, first, S, st)
+    return st
+
+
+def _host(t):
+    import torch as T
+    T.cuda.synchronize()
+    a = t.cpu().numpy()
+    return a.view(np.uint32) if a.dtype == np.int32 else a
+
+
+def _gen(torch, rng, g, st, S, N, dt, offset_words=0, shape=None):
+    out = torch.empty(S * N + offset_words + 4, dtype=torch.int32, device="cuda")
+    view = out[offset_words:offset_words + S * N]
+    if shape is None:
+        rng.rng_generate(g, st, S, N, dt, view)
+    else:
+        rng.rng_generate_ex(g, st, S, N, dt, view, shape[0], shape[1])
+    res = _host(view).reshape(S, N)
+    return res.view(np.float32) if dt == rng.RNG_F32 else res
+
+
+@pytest.mark.parametrize("name", GENS)
+@pytest.mark.parametrize("S,first", [(1, 0), (63, 0), (64, 5), (1000, 0), (4097, 123456)])
+def test_seed_parity(rng, torch, oracle, name, S, first):
+    g = rng.GENERATORS[name]
+    st = _dev_state(torch, rng, g, 77, S, first)
+    ref = oracle.seed(oracle.GENERATORS[name], 77, S, first_stream=first)
+    assert np.array_equal(_host(st), ref)
+
+
+CASES = [(1, 1), (1, 37), (63, 33), (64, 32), (65, 64), (100, 257), (4097, 40), (3, 5000), (1, 70000),
+         (200, 1000)]
+
+
+@pytest.mark.parametrize("name", GENS)
+@pytest.mark.parametrize("dt", ["u32", "f32"])
+@pytest.mark.parametrize("S,N", CASES)
+def test_generate_parity(rng, torch, oracle, name, dt, S, N):
+    g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
+    t = rng.DTYPES[dt]
+    st = _dev_state(torch, rng, g, 1, S)
+    out = _gen(torch, rng, g, st, S, N, t)
+    ref_st = oracle.seed(o, 1, S)
+    ref = oracle.generate(o, ref_st, N, t, threads=4)
+    assert out.dtype == ref.dtype
+    assert np.array_equal(out.view(np.uint32), ref.view(np.uint32))
+    assert np.array_equal(_host(st), ref_st)
+
+
+@pytest.mark.parametrize("name", GENS)
+def test_unaligned_output_and_odd_rows(rng, torch, oracle, name):
+    """4-byte aligned but not 16-byte aligned output, and N not a multiple of 4:
+    the dword store path."""
+    g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
+    for S, N, off in ((130, 64, 1), (130, 66, 0), (70, 35, 3)):
+        st = _dev_state(torch, rng, g, 9, S)
+        out = _gen(torch, rng, g, st, S, N, rng.RNG_U32, offset_words=off)
+        ref = oracle.generate(o, oracle.seed(o, 9, S), N)
+        assert np.array_equal(out, ref)
+
+
+@pytest.mark.parametrize("name", GENS)
+def test_every_launch_shape_same_values(rng, torch, oracle, name):
+    g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
+    S, N = 300, 96
+    ref = oracle.generate(o, oracle.seed(o, 4, S), N, oracle.F32)
+    for wg in (64, 128, 256, 512, 1024):
+        for un in (1, 2, 4, 8, 16):
+            st = _dev_state(torch, rng, g, 4, S)
+            out = _gen(torch, rng, g, st, S, N, rng.RNG_F32, shape=(wg, un))
+            assert np.array_equal(out.view(np.uint32), ref.view(np.uint32)), (wg, un)
+
+
+@pytest.mark.parametrize("name", GENS)
+def test_resume_equals_one_call(rng, torch, oracle, name):
+    """State write-back: generate(N1) then generate(N2) == generate(N1 + N2)."""
+    g = rng.GENERATORS[name]
+    S = 513
+    a = _dev_state(torch, rng, g, 8, S)
+    b = _dev_state(torch, rng, g, 8, S)
+    one = _gen(torch, rng, g, a, S, 300, rng.RNG_U32)
+    p1 = _gen(torch, rng, g, b, S, 123, rng.RNG_U32)
+    p2 = _gen(torch, rng, g, b, S, 177, rng.RNG_U32)
+    assert np.array_equal(one, np.concatenate([p1, p2], axis=1))
+    assert np.array_equal(_host(a), _host(b))
+
+
+@pytest.mark.parametrize("name", GENS)
+def test_run_twice_identical(rng, torch, name):
+    g = rng.GENERATORS[name]
+    S, N = 4096, 512
+    outs = []
+    for _ in range(2):
+        st = _dev_state(torch, rng, g, 3, S)
+        outs.append(_gen(torch, rng, g, st, S, N, rng.RNG_U32))
+    assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("name", GENS)
+@pytest.mark.parametrize("k", [1, 2, 1000, 65536 + 17, (1 << 40) + 7, (1 << 64) - 1])
+def test_skip_parity(rng, torch, oracle, name, k):
+    g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
+    S = 257 if name != "XS256" or k < (1 << 20) else 70
+    st = _dev_state(torch, rng, g, 12, S)
+    rng.rng_skip(g, st, S, k)
+    ref = oracle.skip(o, oracle.seed(o, 12, S), k)
+    assert np.array_equal(_host(st), ref)
+
+
+@pytest.mark.parametrize("name", GENS)
+@pytest.mark.parametrize("total,threads", [(1, 1), (1000, 1), (1000, 7), (4096 * 7 + 3, 64), (100000, 1000),
+                                          (65536, 65536), (5, 8)])
+def test_split_parity(rng, torch, oracle, name, total, threads):
+    """Sequence splitting (Sec. II.A.4): the concatenated thread outputs equal the
+    serial sequence of the one logical stream, and the final state matches."""
+    g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
+    st1 = _dev_state(torch, rng, g, 2, 1)
+    ws_bytes = rng.rng_split_workspace_bytes(g, threads)
+    ws = torch.empty(ws_bytes // 4 + 64, dtype=torch.int32, device="cuda")
+    out = torch.empty(total, dtype=torch.int32, device="cuda")
+    fin = torch.empty(rng.rng_state_words(g), dtype=torch.int32, device="cuda")
+    rng.rng_generate_split(g, st1, total, threads, rng.RNG_U32, out, fin, ws, ws_bytes)
+    ref_st = oracle.seed(o, 2, 1)
+    ref = oracle.generate(o, ref_st, total)[0]
+    assert np.array_equal(_host(out), ref)
+    assert np.array_equal(_host(fin), ref_st[:, 0])
+
+
+@pytest.mark.parametrize("name", ["KISS", "XS256", "MWC32"])
+@pytest.mark.parametrize("S,N", [(1, 2), (1000, 64), (333, 65), (64, 1000), (2, 40000)])
+def test_fused_pi_parity(rng, torch, oracle, name, S, N):
+    g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
+    st = _dev_state(torch, rng, g, 6, S)
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    rng.rng_fused_pi(g, st, S, N, cnt)
+    ref_st = oracle.seed(o, 6, S)
+    ref = oracle.fused_pi(o, ref_st, N, threads=4)
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == ref
+    assert np.array_equal(_host(st), ref_st)
