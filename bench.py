@@ -38,7 +38,11 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-extra", action="store_true", help="skip the side workloads")
-    p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--cpu-seconds", type=float, default=10.0)
+    p.add_argument("--no-tune", action="store_true", help="keep the library's default launch shapes")
+    p.add_argument("--profile", metavar="GEN_DTYPE",
+                   help="counter-collection mode: a 1 GiB device copy (calibration) then 3 launches of "
+                        "one step kernel, e.g. XS256_u32; prints nothing else")
     return p.parse_args()
 
 
@@ -69,6 +73,22 @@ def main():
     torch.cuda.synchronize()
 
     launches = [(n, d) for n in STEP_GENS for d in STEP_DTYPES]
+
+    if args.profile:
+        profile_mode(torch, R, dev, states, out, args.profile)
+        return
+
+    tuned = {}
+    if not args.no_tune:
+        # the library's autotuner picks (workgroup, unroll) per generator and
+        # dtype on this problem; untimed set-up, like any tuning cache
+        for name, d in launches:
+            g = R.GENERATORS[name]
+            scratch = states[name].clone()
+            wg, un, us = R.rng_autotune(g, R.DTYPES[d], S_BULK, N_BULK, scratch, out, 3)
+            tuned["%s_%s" % (name, d)] = {"wg": wg, "unroll": un, "us": round(us, 1)}
+            del scratch
+        torch.cuda.synchronize()
 
     def step(events=None):
         for i, (name, d) in enumerate(launches):
@@ -152,10 +172,11 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(dom_key),
             "bytes_per_launch": dom["bytes"],
             "avg_launch_ms": dom["ms"],
         },
+        "launch_shapes": tuned,
         "write_ceiling": ceil,
         "frac_of_write_ceiling": round(achieved / ceil["best_GB_s"], 4) if ceil else None,
         "per_kernel": {k: {kk: vv for kk, vv in v.items() if kk != "total_ms"} for k, v in per.items()},
@@ -269,13 +290,13 @@ def side_workloads(torch, R, dev, stream):
 
 def cpu_baseline(seconds):
     """The serial oracle on the host's cores over a bounded sample of the step's
-    workload (whole streams of 256 samples, every generator and dtype of the
-    step), scaled to GSamples/s."""
-    import numpy as np
-
+    workload: whole streams of 256 samples for every generator and dtype of the
+    step, streams split over host threads, repeated until about `seconds` of
+    wall time, scaled to GSamples/s."""
     import oracle
     threads = max(1, min(16, os.cpu_count() or 1))
     gens = [(oracle.GENERATORS[n], d) for n in STEP_GENS for d in (oracle.U32, oracle.F32)]
+    oracle.mwc16_table()  # one-time table search, not part of the rate
 
     def run(S):
         t = time.perf_counter()
@@ -284,15 +305,64 @@ def cpu_baseline(seconds):
             oracle.generate(g, st, N_BULK, d, threads=threads)
         return time.perf_counter() - t
 
-    S = 1 << 12
+    S = 1 << 14
     dt = run(S)
     S = int(min(S_BULK, max(S, S * seconds / max(dt, 1e-3))))
     S = max(threads, S // threads * threads)
-    dt = run(S)
-    samples = len(gens) * S * N_BULK
-    return {"value": round(samples / dt / 1e9, 4), "unit": "GSamples/s", "cores": threads, "kind": "oracle",
-            "sample": "%d streams x %d samples for each of %d (generator, dtype) pairs of the step "
-                      "(%.1f s of CPU wall time)" % (S, N_BULK, len(gens), dt)}
+    reps, total_t, samples = 0, 0.0, 0
+    while total_t < seconds * 0.8 and reps < 20:
+        total_t += run(S)
+        samples += len(gens) * S * N_BULK
+        reps += 1
+    return {"value": round(samples / total_t / 1e9, 4), "unit": "GSamples/s", "cores": threads, "kind": "oracle",
+            "sample": "%d pass(es) over %d streams x %d samples for each of %d (generator, dtype) pairs of the "
+                      "step, %.1f s of wall time" % (reps, S, N_BULK, len(gens), total_t)}
+
+
+KERNEL_SOURCES = ["rng_device.hpp", "rng_kernels.hpp", "rng_internal.hpp"]
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1101_1846_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(key):
+    """HBM bytes per launch from the committed counter runs (profiles/traffic.json),
+    or None when they are missing or were taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get("kernels", {}).get(key)
+    if not ent or rec.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def profile_mode(torch, R, dev, states, out, key):
+    """Launch sequence for the counter runs: a plain 1 GiB device-to-device copy
+    (its FETCH_SIZE and WRITE_SIZE calibrate the counters), then three launches
+    of the chosen step kernel."""
+    name, d = key.split("_")
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.int32, device=dev)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    g = R.GENERATORS[name]
+    for _ in range(3):
+        R.rng_generate(g, states[name], S_BULK, N_BULK, R.DTYPES[d], out)
+    torch.cuda.synchronize()
+    print("profile launches done: copy 1 GiB, 3 x k_generate<%s>" % key, flush=True)
 
 
 if __name__ == "__main__":

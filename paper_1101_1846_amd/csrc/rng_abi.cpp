@@ -260,7 +260,7 @@ int generate_impl(int g, int dt, uint32_t *d_state, uint64_t ld, uint64_t S, uin
     a.N = N;
     a.out = d_out;
     a.vec4 = (N % 4 == 0) && (((uintptr_t)d_out & 15) == 0);
-    a.nt = 1;
+    a.nt = 0;  // plain stores: the streaming hint measured slower for these writes
     a.tab = tab;
     choose_chunks(g, S, N, kGenTile, &a.C, &a.P);
     return check_launch(dispatch_generate(g, dt, a, (int)shape.wg, (int)shape.unroll, staged, st),

@@ -12,7 +12,16 @@ enum { RNG_DT_U32 = 0, RNG_DT_F32 = 1 };
 
 // Samples each lane produces into its LDS tile between two transposed
 // stores (the tile is [64][kGenTile + 4] words per wavefront).
-constexpr int kGenTile = 32;
+#ifndef RNGX_GEN_TILE
+#define RNGX_GEN_TILE 64
+#endif
+constexpr int kGenTile = RNGX_GEN_TILE;
+
+// Staged store schedule: 1 = whole tile at once, 2 = software-pipelined.
+#ifndef RNGX_STORE_MODE
+#define RNGX_STORE_MODE 2
+#endif
+constexpr int kStoreMode = RNGX_STORE_MODE;
 
 struct GenArgs {
     uint32_t *state;  // [W][ld]

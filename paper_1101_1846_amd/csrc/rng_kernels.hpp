@@ -66,6 +66,67 @@ __global__ __launch_bounds__(256) void k_tree_level(uint32_t *__restrict__ ws, u
     g.store(ws, T, t);
 }
 
+// ------------------------------------------------------------------ tile store
+// Write a wave's LDS tile [64][K] (row stride K + 4 words) to rows s0.. of the
+// stream-major output, columns k0 .. k0 + cnt.  Consecutive lanes take
+// consecutive 16-byte quads (vec4) or words of one row, so every store
+// instruction covers 64 / (K/4) rows x K words contiguous per row.  Full
+// tiles read every LDS quad first and then issue every store, keeping all of
+// them in flight; partial tiles take a predicated path.
+template <int K>
+__device__ __forceinline__ void store_tile(const uint32_t *tile, uint32_t *out, uint64_t s0, uint64_t N,
+                                           uint64_t k0, uint32_t rows, uint32_t cnt, int lane, uint32_t vec4,
+                                           uint32_t nt)
+{
+    constexpr int LD = K + 4;
+    if (vec4) {
+        constexpr int QPR = K / 4;       // quads per row
+        constexpr int RPI = 64 / QPR;    // rows per store instruction
+        const int r0 = lane / QPR, q = lane % QPR;
+        const uint32_t *src = tile + r0 * LD + 4 * q;
+        uint32_t *dst = out + (s0 + r0) * N + k0 + 4 * q;
+        if (rows == 64 && cnt == K) {
+            u32x4 v[QPR];
+#pragma unroll
+            for (int i = 0; i < QPR; ++i) v[i] = *(const u32x4 *)(src + i * RPI * LD);
+#pragma unroll
+            for (int i = 0; i < QPR; ++i) {
+                u32x4 *d = (u32x4 *)(dst + (uint64_t)(i * RPI) * N);
+                if (nt) __builtin_nontemporal_store(v[i], d);
+                else *d = v[i];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < QPR; ++i) {
+                if ((uint32_t)(r0 + i * RPI) < rows && (uint32_t)(4 * q) < cnt) {
+                    u32x4 val = *(const u32x4 *)(src + i * RPI * LD);
+                    *(u32x4 *)(dst + (uint64_t)(i * RPI) * N) = val;
+                }
+            }
+        }
+    } else {
+        constexpr int RPI = 64 / K;      // rows per store instruction (K <= 64)
+        const int r0 = lane / K, c = lane % K;
+        const uint32_t *src = tile + r0 * LD + c;
+        uint32_t *dst = out + (s0 + r0) * N + k0 + c;
+        if (rows == 64 && cnt == K) {
+            uint32_t v[K];
+#pragma unroll
+            for (int i = 0; i < K; ++i) v[i] = src[i * RPI * LD];
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                uint32_t *d = dst + (uint64_t)(i * RPI) * N;
+                if (nt) __builtin_nontemporal_store(v[i], d);
+                else *d = v[i];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < K; ++i)
+                if ((uint32_t)(r0 + i * RPI) < rows && (uint32_t)c < cnt) dst[(uint64_t)(i * RPI) * N] = src[i * RPI * LD];
+        }
+    }
+}
+
 // ------------------------------------------------------------------ generate
 // Lane mapping: wave w serves streams [64 sb, 64 sb + 64) for chunk j, with
 // sb = w / P and j = w % P.  Chunk j covers samples [j C, min((j+1) C, N)) of
@@ -73,16 +134,37 @@ __global__ __launch_bounds__(256) void k_tree_level(uint32_t *__restrict__ ws, u
 // jump distance is uniform across the wave).  The last chunk writes the
 // state back.
 //
-// Store path (kStaged): each lane produces K consecutive samples of its own
-// stream into a wave-private LDS tile [64][K + 4]; the wave then writes the
-// tile row by row so that consecutive lanes store consecutive addresses of
-// one stream (dwordx4 when rows are 16-byte aligned), instead of 64 lanes
-// each touching a different row.  Without kStaged every lane stores its own
-// row directly from registers.
-template <class G, int DT, int WG, int U, int K, bool kStaged>
+// Store paths.  kMode 0: every lane stores its own row straight from
+// registers.  kMode 1 and 2 stage through a wave-private LDS tile
+// [64][K + 4]: each lane writes K consecutive samples of its own stream, and
+// the wave then stores the tile row by row so that consecutive lanes write
+// consecutive 16-byte quads of one stream (instead of 64 lanes each touching
+// a different row).  kMode 1 issues the whole tile's stores at once after
+// generating it; kMode 2 software-pipelines: the transposed quads of tile t
+// are held in VGPRs and their stores are spread evenly through the
+// generation of tile t + 1, so the write stream leaves the CU at a steady
+// rate while the VALU keeps generating.
+template <class G, int DT, int U>
+__device__ __forceinline__ void gen_to_row(G &g, uint32_t *row, int k)
+{
+    uint32_t v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = out_bits<DT>(g.next());
+    if constexpr (U % 4 == 0) {
+#pragma unroll
+        for (int u = 0; u < U; u += 4) *(uint4 *)&row[k + u] = make_uint4(v[u], v[u + 1], v[u + 2], v[u + 3]);
+    } else if constexpr (U == 2) {
+        *(uint2 *)&row[k] = make_uint2(v[0], v[1]);
+    } else {
+        row[k] = v[0];
+    }
+}
+
+template <class G, int DT, int WG, int U, int K, int kMode>
 __global__ __launch_bounds__(WG) void k_generate(GenArgs a)
 {
     static_assert(K % U == 0 && K % 4 == 0, "tile depth");
+    constexpr bool kStaged = kMode != 0;
     constexpr int LD = K + 4;
     constexpr int NW = WG / 64;
     __shared__ __attribute__((aligned(16))) uint32_t lds[kStaged ? NW * 64 * LD : 1];
@@ -107,55 +189,56 @@ __global__ __launch_bounds__(WG) void k_generate(GenArgs a)
     uint32_t *tile = kStaged ? &lds[wv * 64 * LD] : nullptr;
     uint32_t *out = (uint32_t *)a.out;
     const uint64_t N = a.N;
+    uint64_t k0 = kb;
 
-    for (uint64_t k0 = kb; k0 < ke; k0 += K) {
+    if constexpr (kMode == 2) {
+        if (a.vec4 && rows == 64 && k0 + K <= ke) {
+            constexpr int QPR = K / 4, RPI = 64 / QPR;
+            const int r0 = lane / QPR, q = lane % QPR;
+            const uint32_t *src = tile + r0 * LD + 4 * q;
+            uint32_t *row = tile + lane * LD;
+            u32x4 P[QPR];
+            // first tile: generate only
+#pragma unroll
+            for (int k = 0; k < K; k += U) gen_to_row<G, DT, U>(g, row, k);
+            RNGX_COMPILER_FENCE();
+#pragma unroll
+            for (int i = 0; i < QPR; ++i) P[i] = *(const u32x4 *)(src + i * RPI * LD);
+            RNGX_COMPILER_FENCE();
+            uint32_t *pdst = out + (s0 + r0) * N + k0 + 4 * q;
+            for (k0 += K; k0 + K <= ke; k0 += K) {
+#pragma unroll
+                for (int k = 0; k < K; k += U) {
+                    gen_to_row<G, DT, U>(g, row, k);
+#pragma unroll
+                    for (int i = k * QPR / K; i < (k + U) * QPR / K; ++i)
+                        *(u32x4 *)(pdst + (uint64_t)(i * RPI) * N) = P[i];
+                    // keep each group of stores between its generation chunks
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                RNGX_COMPILER_FENCE();
+#pragma unroll
+                for (int i = 0; i < QPR; ++i) P[i] = *(const u32x4 *)(src + i * RPI * LD);
+                RNGX_COMPILER_FENCE();
+                pdst += K;
+            }
+#pragma unroll
+            for (int i = 0; i < QPR; ++i) *(u32x4 *)(pdst + (uint64_t)(i * RPI) * N) = P[i];
+        }
+    }
+
+    for (; k0 < ke; k0 += K) {
         const uint32_t cnt = (uint32_t)min<uint64_t>(K, ke - k0);
         if constexpr (kStaged) {
             uint32_t *row = tile + lane * LD;
             if (cnt == K) {
 #pragma unroll 1
-                for (int k = 0; k < K; k += U) {
-                    uint32_t v[U];
-#pragma unroll
-                    for (int u = 0; u < U; ++u) v[u] = out_bits<DT>(g.next());
-                    if constexpr (U % 4 == 0) {
-#pragma unroll
-                        for (int u = 0; u < U; u += 4)
-                            *(uint4 *)&row[k + u] = make_uint4(v[u], v[u + 1], v[u + 2], v[u + 3]);
-                    } else if constexpr (U == 2) {
-                        *(uint2 *)&row[k] = make_uint2(v[0], v[1]);
-                    } else {
-                        row[k] = v[0];
-                    }
-                }
+                for (int k = 0; k < K; k += U) gen_to_row<G, DT, U>(g, row, k);
             } else {
                 for (uint32_t k = 0; k < cnt; ++k) row[k] = out_bits<DT>(g.next());
             }
             RNGX_COMPILER_FENCE();
-            if (a.vec4) {
-                constexpr int QPR = K / 4;  // 16-byte quads per row
-#pragma unroll
-                for (int i = 0; i < QPR; ++i) {
-                    const int f = i * 64 + lane, r = f / QPR, q = f % QPR;
-                    if ((uint32_t)r < rows && (uint32_t)(4 * q) < cnt) {
-                        u32x4 val = *(const u32x4 *)&tile[r * LD + 4 * q];
-                        u32x4 *dst = (u32x4 *)(out + (s0 + r) * N + k0 + 4 * q);
-                        if (a.nt) __builtin_nontemporal_store(val, dst);
-                        else *dst = val;
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int i = 0; i < K; ++i) {
-                    const int f = i * 64 + lane, r = f / K, c = f % K;
-                    if ((uint32_t)r < rows && (uint32_t)c < cnt) {
-                        uint32_t val = tile[r * LD + c];
-                        uint32_t *dst = out + (s0 + r) * N + k0 + c;
-                        if (a.nt) __builtin_nontemporal_store(val, dst);
-                        else *dst = val;
-                    }
-                }
-            }
+            store_tile<K>(tile, out, s0, N, k0, rows, cnt, lane, a.vec4, a.nt);
             RNGX_COMPILER_FENCE();
         } else {
             uint32_t *dst = out + s * N + k0;
@@ -296,26 +379,29 @@ int launch_state_copy_t(const uint32_t *src, uint64_t ss, uint64_t si, uint32_t 
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <class G, int DT, int WG, int U, bool kStaged>
+template <class G, int DT, int WG, int U, int kMode>
 int launch_generate_shape(const GenArgs &a, hipStream_t stream)
 {
     uint64_t waves = ((a.S + 63) / 64) * a.P;
     uint64_t blocks = (waves + WG / 64 - 1) / (WG / 64);
-    hipLaunchKernelGGL((k_generate<G, DT, WG, U, kGenTile, kStaged>), dim3((unsigned)blocks), dim3(WG), 0,
-                       stream, a);
+    // tile depth: kGenTile unless the workgroup's tiles would not fit in the
+    // 160 KiB of LDS, then 32 (chunk lengths are multiples of kGenTile, so
+    // of both depths)
+    constexpr int K = (WG * (kGenTile + 4) * 4 <= 160 * 1024) ? kGenTile : 32;
+    hipLaunchKernelGGL((k_generate<G, DT, WG, U, K, kMode>), dim3((unsigned)blocks), dim3(WG), 0, stream, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <class G, int DT, int WG>
 int launch_generate_u(const GenArgs &a, int unroll, bool staged, hipStream_t stream)
 {
-    if (!staged) return launch_generate_shape<G, DT, WG, 8, false>(a, stream);
+    if (!staged) return launch_generate_shape<G, DT, WG, 8, 0>(a, stream);
     switch (unroll) {
-    case 1: return launch_generate_shape<G, DT, WG, 1, true>(a, stream);
-    case 2: return launch_generate_shape<G, DT, WG, 2, true>(a, stream);
-    case 4: return launch_generate_shape<G, DT, WG, 4, true>(a, stream);
-    case 8: return launch_generate_shape<G, DT, WG, 8, true>(a, stream);
-    case 16: return launch_generate_shape<G, DT, WG, 16, true>(a, stream);
+    case 1: return launch_generate_shape<G, DT, WG, 1, kStoreMode>(a, stream);
+    case 2: return launch_generate_shape<G, DT, WG, 2, kStoreMode>(a, stream);
+    case 4: return launch_generate_shape<G, DT, WG, 4, kStoreMode>(a, stream);
+    case 8: return launch_generate_shape<G, DT, WG, 8, kStoreMode>(a, stream);
+    case 16: return launch_generate_shape<G, DT, WG, 16, kStoreMode>(a, stream);
     }
     return -2;
 }

@@ -1,0 +1,90 @@
+"""Summaries of rocprofv3 result databases (the rocpd SQLite files written by
+``rocprofv3 -d DIR -o run``): kernel-trace statistics and per-dispatch PMC
+counters, as short text tables.
+
+    python -m paper_1101_1846_amd.prof trace RUN_results.db
+    python -m paper_1101_1846_amd.prof pmc FETCH_results.db WRITE_results.db KEY
+
+The ``pmc`` form scales each counter by what it reads for the plain 1 GiB
+device-to-device copy that ``bench.py --profile KEY`` launches first (the copy
+moves exactly 2^30 bytes each way), and prints the JSON record that
+``profiles/traffic.json`` keeps for that kernel.
+"""
+import json
+import sqlite3
+import sys
+from collections import defaultdict
+
+COPY_BYTES = 1 << 30
+
+
+def _rows(db, sql):
+    con = sqlite3.connect(db)
+    try:
+        return list(con.execute(sql))
+    finally:
+        con.close()
+
+
+def short(name, width=96):
+    name = name.replace("rngx::", "").replace("(GenArgs)", "")
+    return name if len(name) <= width else name[: width - 3] + "..."
+
+
+def trace_table(db):
+    """Per kernel: calls, total/avg/min/max duration in microseconds."""
+    stats = defaultdict(list)
+    for name, dur in _rows(db, "select name, duration from kernels"):
+        stats[name].append(dur / 1000.0)
+    lines = ["| kernel | calls | total us | avg us | min us | max us |", "|---|---|---|---|---|---|"]
+    for name, d in sorted(stats.items(), key=lambda kv: -sum(kv[1])):
+        lines.append("| %s | %d | %.1f | %.2f | %.2f | %.2f |" % (short(name), len(d), sum(d), sum(d) / len(d),
+                                                                  min(d), max(d)))
+    return "\n".join(lines), stats
+
+
+def pmc_per_dispatch(db, counter):
+    """[(kernel name, grid size, value in KiB)] in dispatch order."""
+    return [(n, g, v) for n, g, v in _rows(
+        db, "select kernel_name, grid_size, value from counters_collection where counter_name = '%s' "
+            "order by dispatch_id" % counter)]
+
+
+def copy_value(rows):
+    vals = [v for n, g, v in rows if "copy" in n.lower() or "elementwise" in n.lower()]
+    return vals[-1] if vals else None
+
+
+def pmc_record(fetch_db, write_db, key):
+    f = pmc_per_dispatch(fetch_db, "FETCH_SIZE")
+    w = pmc_per_dispatch(write_db, "WRITE_SIZE")
+    fc, wc = copy_value(f), copy_value(w)
+    fs = COPY_BYTES / (fc * 1024.0)
+    ws = COPY_BYTES / (wc * 1024.0)
+    kf = [v for n, g, v in f if "k_generate" in n][-3:]
+    kw = [v for n, g, v in w if "k_generate" in n][-3:]
+    fetch = sum(kf) / len(kf) * 1024.0 * fs
+    write = sum(kw) / len(kw) * 1024.0 * ws
+    return {
+        "copy_calibration": {"bytes_each_way": COPY_BYTES, "FETCH_SIZE_KiB": fc, "WRITE_SIZE_KiB": wc,
+                             "fetch_scale": round(fs, 4), "write_scale": round(ws, 4)},
+        "FETCH_SIZE_KiB_per_launch": [round(v, 1) for v in kf],
+        "WRITE_SIZE_KiB_per_launch": [round(v, 1) for v in kw],
+        "hbm_fetch_bytes_per_launch": int(fetch),
+        "hbm_write_bytes_per_launch": int(write),
+        "hbm_bytes_per_launch": int(fetch + write),
+    }
+
+
+def main(argv):
+    if argv[0] == "trace":
+        table, _ = trace_table(argv[1])
+        print(table)
+    elif argv[0] == "pmc":
+        print(json.dumps({argv[3]: pmc_record(argv[1], argv[2], argv[3])}, indent=1))
+    else:
+        raise SystemExit(__doc__)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

@@ -1,0 +1,125 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py times.
+
+- MWC32, 4096 streams x 1024 (base 2^32), states from SplitMix64(0): every sample.
+- Bulk store mode, 2^20 streams x 256, XS256 / XS32 / KISS / MWC1616, uint32 and
+  FP32, states from SplitMix64(1): every sample and every final state.
+- Sequence splitting of one 2^30-sample MWC32 and XS256 sequence over 2^20
+  threads: 10^6 uniformly drawn positions plus the first and last 2^20 samples
+  and the final state, against one serial pass of the oracle.
+- Fused consumer over 2^34 KISS samples (2^20 streams x 2^14): the exact count
+  and every final state.
+"""
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+THREADS = max(1, min(16, os.cpu_count() or 1))
+
+
+@pytest.fixture(scope="module")
+def rng():
+    import paper_1101_1846_amd as R
+    R.rng_init()
+    return R
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available()
+    return T
+
+
+def _u32(t):
+    import torch as T
+    T.cuda.synchronize()
+    return t.cpu().numpy().view(np.uint32)
+
+
+def test_mwc32_4096x1024(rng, torch, oracle):
+    g, S, N = rng.RNG_MWC32, 4096, 1024
+    st = torch.empty((2, S), dtype=torch.int32, device="cuda")
+    rng.rng_seed(g, 0, 0, S, st)
+    out = torch.empty((S, N), dtype=torch.int32, device="cuda")
+    rng.rng_generate(g, st, S, N, rng.RNG_U32, out)
+    ref_st = oracle.seed(oracle.MWC32, 0, S)
+    ref = oracle.generate(oracle.MWC32, ref_st, N, threads=THREADS)
+    assert np.array_equal(_u32(out), ref)
+    assert np.array_equal(_u32(st), ref_st)
+
+
+@pytest.mark.parametrize("name", ["XS256", "XS32", "KISS", "MWC1616"])
+@pytest.mark.parametrize("dt", ["u32", "f32"])
+def test_bulk_2p20_streams_x256(rng, torch, oracle, name, dt):
+    g, o, t = rng.GENERATORS[name], oracle.GENERATORS[name], rng.DTYPES[dt]
+    S, N = 1 << 20, 256
+    st = torch.empty((rng.rng_state_words(g), S), dtype=torch.int32, device="cuda")
+    rng.rng_seed(g, 1, 0, S, st)
+    out = torch.empty(S * N, dtype=torch.int32, device="cuda")
+    rng.rng_generate(g, st, S, N, t, out)
+    got = _u32(out).reshape(S, N)
+    ref_st = oracle.seed(o, 1, S)
+    ref = oracle.generate(o, ref_st, N, t, threads=THREADS)
+    assert np.array_equal(got, ref.view(np.uint32))
+    assert np.array_equal(_u32(st), ref_st)
+
+
+@pytest.mark.parametrize("name", ["MWC32", "XS256"])
+def test_split_2p30_over_2p20_threads(rng, torch, oracle, name):
+    g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
+    total, T = 1 << 30, 1 << 20
+    W = rng.rng_state_words(g)
+    s1 = torch.empty(W, dtype=torch.int32, device="cuda")
+    rng.rng_seed(g, 2, 0, 1, s1)
+    fin = torch.empty(W, dtype=torch.int32, device="cuda")
+    wsb = rng.rng_split_workspace_bytes(g, T)
+    ws = torch.empty(wsb // 4, dtype=torch.int32, device="cuda")
+    out = torch.empty(total, dtype=torch.int32, device="cuda")
+    rng.rng_generate_split(g, s1, total, T, rng.RNG_U32, out, fin, ws, wsb)
+    pos = np.sort(np.random.default_rng(3).integers(0, total, 10 ** 6, dtype=np.int64))
+    idx = torch.from_numpy(pos).to("cuda")
+    got_pos = _u32(out[idx])
+    head = _u32(out[: 1 << 20])
+    tail = _u32(out[total - (1 << 20):])
+    one = oracle.seed(o, 2, 1)[:, 0].copy()
+    ref_pos, ref_head, ref_tail = oracle.serial_sample(o, one, total, pos.astype(np.uint64), 1 << 20, 1 << 20)
+    assert np.array_equal(got_pos, ref_pos)
+    assert np.array_equal(head, ref_head)
+    assert np.array_equal(tail, ref_tail)
+    assert np.array_equal(_u32(fin), one)
+
+
+def test_fused_pi_2p34_kiss(rng, torch, oracle):
+    g = rng.RNG_KISS
+    S, N = 1 << 20, 1 << 14
+    st = torch.empty((6, S), dtype=torch.int32, device="cuda")
+    rng.rng_seed(g, 6, 0, S, st)
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    rng.rng_fused_pi(g, st, S, N, cnt)
+    ref_st = oracle.seed(oracle.KISS, 6, S)
+    ref = oracle.fused_pi(oracle.KISS, ref_st, N, threads=THREADS)
+    torch.cuda.synchronize()
+    c = int(cnt.item())
+    assert c == ref
+    assert np.array_equal(_u32(st), ref_st)
+    pairs = S * N // 2
+    p = np.pi / 4
+    assert abs(4 * c / pairs - np.pi) < 6 * 4 * np.sqrt(p * (1 - p) / pairs)
+
+
+def test_autotune_keeps_values(rng, torch, oracle):
+    g, S, N = rng.RNG_XS32, 1 << 16, 256
+    st = torch.empty((1, S), dtype=torch.int32, device="cuda")
+    out = torch.empty(S * N, dtype=torch.int32, device="cuda")
+    old = rng.rng_get_shape(g, rng.RNG_U32)
+    wg, un, us = rng.rng_autotune(g, rng.RNG_U32, S, N, st, out, 2)
+    assert wg in (64, 128, 256, 512, 1024) and un in (1, 2, 4, 8, 16) and us > 0
+    assert rng.rng_get_shape(g, rng.RNG_U32) == (wg, un)
+    rng.rng_seed(g, 5, 0, S, st)
+    rng.rng_generate(g, st, S, N, rng.RNG_U32, out)
+    ref = oracle.generate(oracle.XS32, oracle.seed(oracle.XS32, 5, S), N)
+    assert np.array_equal(_u32(out).reshape(S, N), ref)
+    rng.rng_set_shape(g, rng.RNG_U32, *old)
