@@ -40,6 +40,8 @@ def parse():
     p.add_argument("--no-extra", action="store_true", help="skip the side workloads")
     p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--no-tune", action="store_true", help="keep the library's default launch shapes")
+    p.add_argument("--only", choices=["batched", "served", "split", "fused", "small"],
+                   help="run one side workload alone and print its JSON record")
     p.add_argument("--profile", metavar="GEN_DTYPE",
                    help="counter-collection mode: a 1 GiB device copy (calibration) then 3 launches of "
                         "one step kernel, e.g. XS256_u32; prints nothing else")
@@ -61,6 +63,9 @@ def main():
     dev = torch.device("cuda:0")
     R.rng_init()
     stream = torch.cuda.current_stream()
+    if args.only:
+        print(json.dumps(side_workloads(torch, R, dev, stream, only=args.only)))
+        return
 
     # ---------------------------------------------------------------- inputs
     states = {}
@@ -181,6 +186,8 @@ def main():
         "frac_of_write_ceiling": round(achieved / ceil["best_GB_s"], 4) if ceil else None,
         "per_kernel": {k: {kk: vv for kk, vv in v.items() if kk != "total_ms"} for k, v in per.items()},
         "side_workloads": extra,
+        "served_latency_us": {k: {"p50": v["p50_us"], "p99": v["p99_us"]}
+                              for k, v in extra.get("served", {}).items()},
         "cpu_baseline": cpu,
         "wall_s_timed": round(wall, 3),
     }
@@ -238,8 +245,14 @@ def _time(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def side_workloads(torch, R, dev, stream):
+def side_workloads(torch, R, dev, stream, only=None):
     res = {}
+    if only == "batched":
+        res["batched_10k_requests"] = batched_workload(torch, R, dev)
+        return res
+    if only == "served":
+        res["served"] = served_workload(R, batched_workload(torch, R, dev)["single_large_call_GSamples_s"])
+        return res
     # MWC32, 4096 streams x 1024 (small, launch-bound; chunked by jump-ahead)
     g = R.RNG_MWC32
     S, N = 4096, 1024
@@ -276,6 +289,8 @@ def side_workloads(torch, R, dev, stream):
                                        "GSamples_s": round(total / (ms * 1e-3) / 1e9, 1),
                                        "GB_s": round(4 * total / (ms * 1e-3) / 1e9, 1)}
     del o
+    res["batched_10k_requests"] = batched_workload(torch, R, dev)
+    res["served"] = served_workload(R, res["batched_10k_requests"]["single_large_call_GSamples_s"])
     # fused pi over 2^34 KISS samples (no stores: integer-VALU bound)
     g = R.RNG_KISS
     S, N = 1 << 20, 1 << 14
@@ -286,6 +301,106 @@ def side_workloads(torch, R, dev, stream):
     res["fused_pi_kiss_2^34"] = {"ms": round(ms, 3), "GSamples_s": round(S * N / (ms * 1e-3) / 1e9, 1)}
     torch.cuda.empty_cache()
     return res
+
+
+def batch_pools(torch, R, dev, tab, seed=5):
+    """Per-generator state pools [words][n_g] seeded from SplitMix64(seed), and the
+    (pointer, stride) of every request's stream inside them."""
+    names = tab["generators"]
+    pools, where = {}, []
+    counts = {g: int((tab["gen"] == i).sum()) for i, g in enumerate(names)}
+    for g, c in counts.items():
+        if c:
+            gid = R.GENERATORS[g]
+            st = torch.empty((R.rng_state_words(gid), c), dtype=torch.int32, device=dev)
+            R.rng_seed(gid, seed, 0, c, st)
+            pools[g] = st
+    seen = {g: 0 for g in names}
+    for gi in tab["gen"]:
+        g = names[gi]
+        where.append((pools[g].data_ptr() + 4 * seen[g], counts[g], seen[g]))
+        seen[g] += 1
+    return pools, where
+
+
+def batched_workload(torch, R, dev, reps=5):
+    """10,000 independent requests (generator uniform over MWC32/XS256/KISS,
+    dtype 50/50, length log-uniform in [2^8, 2^22]) in one persistent launch
+    replayed from a HIP graph; compared with the same samples generated by one
+    large rng_generate call per (generator, dtype)."""
+    from paper_1101_1846_amd import workloads as W
+    tab = W.batch_table(10000, seed=4)
+    names = tab["generators"]
+    pools, where = batch_pools(torch, R, dev, tab)
+    offs, words = W.layout_outputs(tab["length"])
+    out = torch.empty(words, dtype=torch.int32, device=dev)
+    base = out.data_ptr()
+    reqs = [(R.GENERATORS[names[g]], int(d), p, stride, 0, int(n), base + 4 * int(o))
+            for g, d, (p, stride, _), n, o in zip(tab["gen"], tab["dtype"], where, tab["length"], offs)]
+    total = int(tab["length"].sum())
+    h = R.rng_batch_create(len(reqs), total)
+    try:
+        R.rng_batch_set(h, reqs)
+        wg, un, chunk, tune_us = R.rng_batch_autotune(h, reps=1)
+        ms = _time(torch, lambda: R.rng_batch_launch(h), reps)
+    finally:
+        R.rng_batch_destroy(h)
+    # single large calls over the same per-(generator, dtype) sample counts
+    single_ms = 0.0
+    S = 1 << 20
+    for gi, g in enumerate(names):
+        gid = R.GENERATORS[g]
+        st = torch.empty((R.rng_state_words(gid), S), dtype=torch.int32, device=dev)
+        R.rng_seed(gid, 9, 0, S, st)
+        for d in (0, 1):
+            n_g = int(tab["length"][(tab["gen"] == gi) & (tab["dtype"] == d)].sum())
+            N = max(64, round(n_g / S / 64) * 64)  # rows a multiple of the 64-sample tile
+            single_ms += _time(torch, lambda: R.rng_generate(gid, st, S, N, d, out), 3) * n_g / (S * N)
+    del out
+    torch.cuda.empty_cache()
+    rate = total / (ms * 1e-3) / 1e9
+    single = total / (single_ms * 1e-3) / 1e9
+    return {"requests": len(reqs), "samples": total, "bytes": 4 * total, "ms_per_batch": round(ms, 3),
+            "GSamples_s": round(rate, 1), "GB_s": round(4 * total / (ms * 1e-3) / 1e9, 1),
+            "single_large_call_GSamples_s": round(single, 1), "frac_of_single_call": round(rate / single, 4),
+            "shape": {"wg": wg, "unroll": un, "chunk": chunk}}
+
+
+def served_workload(R, single_rate):
+    """Poisson arrivals at 2k, 20k and 200k requests/s over 10^6 resident streams
+    (generator = stream id mod 3 over MWC32/XS256/KISS), sizes log-uniform in
+    [2^10, 2^24] samples, dtype 50/50, a 16 GiB output pool for admission, three
+    batches in flight; then a saturating burst of 20,000 requests."""
+    from paper_1101_1846_amd import workloads as W
+    gens = [R.GENERATORS[g] for g in ("MWC32", "XS256", "KISS")]
+    h = R.rng_server_create(10 ** 6, gens, 8, 16 << 30, 4096, 1 << 31, inflight=3, auto_release=True)
+    out = {}
+    try:
+        for lam, dur in ((2000, 1.0), (20000, 0.5), (200000, 0.25)):
+            n = int(lam * dur)
+            tab = W.served_table(n, seed=7)
+            t = W.poisson_arrivals(lam, n, seed=7)
+            R.rng_server_reset_stats(h)
+            R.rng_server_replay(h, t, tab["stream"], tab["length"], tab["dtype"])
+            st = R.rng_server_stats(h)
+            out["lambda_%d" % lam] = {
+                "requests": n, "p50_us": round(st["p50_us"], 1), "p99_us": round(st["p99_us"], 1),
+                "mean_us": round(st["mean_us"], 1), "offered_GB_s": round(4 * tab["length"].sum() / t[-1] / 1e9, 1),
+                "GSamples_s": round(st["gsamples_per_s"], 1), "batches": st["batches"],
+                "mean_batch_requests": round(st["mean_batch_requests"], 1)}
+        n = 20000
+        tab = W.served_table(n, seed=17)
+        R.rng_server_reset_stats(h)
+        R.rng_server_replay(h, [0.0] * n, tab["stream"], tab["length"], tab["dtype"])
+        st = R.rng_server_stats(h)
+        out["saturation_burst_20000"] = {
+            "GSamples_s": round(st["gsamples_per_s"], 1), "GB_s": round(4 * st["gsamples_per_s"], 1),
+            "frac_of_single_call": round(st["gsamples_per_s"] / single_rate, 4),
+            "p50_us": round(st["p50_us"], 1), "p99_us": round(st["p99_us"], 1), "batches": st["batches"],
+            "mean_batch_requests": round(st["mean_batch_requests"], 1), "admission_waits": st["admission_waits"]}
+    finally:
+        R.rng_server_destroy(h)
+    return out
 
 
 def cpu_baseline(seconds):

@@ -146,6 +146,110 @@ int rng_generate_split(int g, const uint32_t *d_state_one, uint64_t total, uint6
 int rng_fused_pi(int g, uint32_t *d_state, uint64_t n_streams, uint64_t n,
                  uint64_t *d_count, void *stream);
 
+/* ---------------------------------------------------------------------- */
+/* Batched generation: thousands of independent requests of uneven length  */
+/* in one persistent launch captured in a HIP graph.  Each request is the   */
+/* slice [offset, offset + length) of one stream's serial sequence; the     */
+/* stream's state is advanced by offset + length.  Requests are cut into    */
+/* chunks of C samples whose start states come from jump-ahead (one jump    */
+/* per request, then a doubling tree with one uniform jump per chunk); a    */
+/* persistent kernel pulls 64-chunk tiles from an atomic counter.           */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t gen;            /* rng_gen_t */
+    int32_t dtype;          /* rng_dtype_t */
+    uint32_t *d_state;      /* word 0 of the stream's state (device), in/out */
+    uint64_t state_stride;  /* word stride of that state: 1 for a contiguous
+                               [words] state, n_streams for stream s of a
+                               [words][n_streams] pool (d_state = pool + s) */
+    uint64_t offset;        /* samples skipped before the first output */
+    uint64_t length;        /* samples produced (0: only the skip) */
+    void *d_out;            /* [length] outputs of dtype, 4-byte aligned; a
+                               128-byte aligned d_out keeps every chunk's
+                               stores on whole cache lines (the fast path:
+                               misaligned rows write partial lines and run
+                               up to 2x slower) */
+} rng_request_t;
+
+typedef struct rng_batch rng_batch_t;
+
+/* A batch handle for up to max_requests requests of at most max_samples
+ * samples in total; it owns its device workspace (chunk states, plan) and
+ * pinned staging buffers, and its graphs.  Created on the current device. */
+int rng_batch_create(uint32_t max_requests, uint64_t max_samples, rng_batch_t **h);
+/* Plan a batch from a host table of n requests (copied; the caller may reuse
+ * its table).  No two requests may share a stream state.  Blocks until the
+ * previous launch's plan upload has left the staging buffers. */
+int rng_batch_set(rng_batch_t *h, const rng_request_t *h_reqs, uint32_t n);
+/* Queue the planned batch on stream: plan upload, then the graph (counter
+ * reset, root jumps, tree levels, persistent generation). */
+int rng_batch_launch(rng_batch_t *h, void *stream);
+/* Persistent-kernel shape: wg lanes per workgroup (64..512), unroll
+ * (samples per generation step) and chunk length C (a multiple of 64);
+ * 0 keeps the current value.  Changing C requires a new rng_batch_set. */
+int rng_batch_set_shape(rng_batch_t *h, uint32_t wg, uint32_t unroll, uint32_t chunk);
+int rng_batch_get_shape(rng_batch_t *h, uint32_t *wg, uint32_t *unroll, uint32_t *chunk);
+/* Time the planned batch under every persistent-kernel shape (wg x unroll)
+ * and chunk length in {512, 1024, 2048, 4096}, reps launches each, and keep
+ * the fastest.  Every trial launch runs the batch, so the request states
+ * advance and the outputs are overwritten. */
+int rng_batch_autotune(rng_batch_t *h, uint32_t reps, uint32_t *best_wg, uint32_t *best_unroll,
+                       uint32_t *best_chunk, float *best_us, void *stream);
+int rng_batch_destroy(rng_batch_t *h);
+
+/* ---------------------------------------------------------------------- */
+/* Serving: a request loop over resident stream states with continuous     */
+/* batching.  A worker thread admits queued requests while output memory    */
+/* (a device pool) and in-flight slots allow, launches each admitted set as */
+/* one batch on one of `inflight` HIP streams (batches overlap on the       */
+/* device), and stamps each request's completion.  Requests for the same   */
+/* stream are served in arrival order, so request i of a stream returns the */
+/* samples [L_0 + ... + L_{i-1}, + L_i) of that stream's serial sequence.   */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+    uint64_t n_streams;            /* resident streams; stream s runs gens[s % n_gens] */
+    int32_t gens[5];
+    uint32_t n_gens;
+    uint64_t seed;                 /* generator kind k is seeded from SplitMix64(seed + k),
+                                      stream s being entry s / n_gens of its kind's pool */
+    uint64_t pool_bytes;           /* output memory budget used for admission */
+    uint32_t max_batch_requests;   /* per launched batch */
+    uint64_t max_batch_samples;    /* per launched batch; also the largest request */
+    uint32_t inflight;             /* batches in flight, 1..8 */
+    uint32_t auto_release;         /* 1: free each output as soon as it completes */
+} rng_server_config_t;
+
+typedef struct {
+    uint64_t submitted, completed, batches, samples, admission_waits;
+    double p50_us, p99_us, mean_us, max_us;  /* arrival -> completion latency */
+    double wall_s;                           /* first arrival -> last completion */
+    double gsamples_per_s;
+    double mean_batch_requests;
+} rng_server_stats_t;
+
+typedef struct rng_server rng_server_t;
+
+int rng_server_create(const rng_server_config_t *cfg, rng_server_t **h);
+/* Queue one request (thread-safe); *ticket identifies it. */
+int rng_server_submit(rng_server_t *h, uint64_t stream_id, uint64_t length, int dtype, uint64_t *ticket);
+/* RNG_OK with *done = 1 and *d_out = its device output once complete (NULL if
+ * released), RNG_EAGAIN with *done = 0 before. */
+int rng_server_poll(rng_server_t *h, uint64_t ticket, int *done, void **d_out);
+/* Return a completed request's output memory to the pool. */
+int rng_server_release(rng_server_t *h, uint64_t ticket);
+/* Block until every submitted request has completed. */
+int rng_server_drain(rng_server_t *h);
+/* Copy one idle stream's resident state to the host ([words] uint32): the
+ * resident states are the server's checkpoint. */
+int rng_server_read_state(rng_server_t *h, uint64_t stream_id, uint32_t *h_state);
+int rng_server_stats(rng_server_t *h, rng_server_stats_t *st);
+int rng_server_reset_stats(rng_server_t *h);
+/* Submit n requests at the given arrival times (seconds from the call,
+ * ascending) in real time, then drain; tickets (may be NULL) receives their ids. */
+int rng_server_replay(rng_server_t *h, const double *t_arrival_s, const uint64_t *stream_ids,
+                      const uint64_t *lengths, const int32_t *dtypes, uint64_t n, uint64_t *tickets);
+int rng_server_destroy(rng_server_t *h);
+
 #ifdef __cplusplus
 }
 #endif

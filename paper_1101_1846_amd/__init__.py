@@ -23,7 +23,7 @@ DTYPES = {"u32": RNG_U32, "f32": RNG_F32}
 RNG_OK, RNG_EINVAL, RNG_ERANGE, RNG_ENOMEM, RNG_EHIP, RNG_ENODEV, RNG_EAGAIN = 0, -1, -2, -3, -4, -5, -6
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError("librng_mi355x.so is not built; run `python -m paper_1101_1846_amd.build` "
+    raise ImportError("librng_mi355x.so is not built; run `python paper_1101_1846_amd/build.py` "
                       "(hipcc --offload-arch=gfx950)")
 
 _lib = ctypes.CDLL(LIB_PATH)
@@ -53,6 +53,57 @@ _SIGS = {
     "rng_generate_split": (_int, [_int, _vp, _u64, _u64, _int, _vp, _vp, _vp, _u64, _vp]),
     "rng_fused_pi": (_int, [_int, _vp, _u64, _u64, _vp, _vp]),
 }
+
+
+class rng_request_t(ctypes.Structure):
+    """One batched request (mirrors rng_request_t of include/rng.h)."""
+    _fields_ = [("gen", ctypes.c_int32), ("dtype", ctypes.c_int32), ("d_state", ctypes.c_void_p),
+                ("state_stride", ctypes.c_uint64), ("offset", ctypes.c_uint64), ("length", ctypes.c_uint64),
+                ("d_out", ctypes.c_void_p)]
+
+
+_SIGS.update({
+    "rng_batch_create": (_int, [_u32, _u64, ctypes.POINTER(_vp)]),
+    "rng_batch_set": (_int, [_vp, ctypes.POINTER(rng_request_t), _u32]),
+    "rng_batch_launch": (_int, [_vp, _vp]),
+    "rng_batch_set_shape": (_int, [_vp, _u32, _u32, _u32]),
+    "rng_batch_get_shape": (_int, [_vp, _pu32, _pu32, _pu32]),
+    "rng_batch_destroy": (_int, [_vp]),
+    "rng_batch_autotune": (_int, [_vp, _u32, _pu32, _pu32, _pu32, ctypes.POINTER(ctypes.c_float), _vp]),
+})
+
+
+class rng_server_config_t(ctypes.Structure):
+    """Mirrors rng_server_config_t of include/rng.h."""
+    _fields_ = [("n_streams", ctypes.c_uint64), ("gens", ctypes.c_int32 * 5), ("n_gens", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64), ("pool_bytes", ctypes.c_uint64), ("max_batch_requests", ctypes.c_uint32),
+                ("max_batch_samples", ctypes.c_uint64), ("inflight", ctypes.c_uint32),
+                ("auto_release", ctypes.c_uint32)]
+
+
+class rng_server_stats_t(ctypes.Structure):
+    """Mirrors rng_server_stats_t of include/rng.h."""
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("samples", ctypes.c_uint64), ("admission_waits", ctypes.c_uint64), ("p50_us", ctypes.c_double),
+                ("p99_us", ctypes.c_double), ("mean_us", ctypes.c_double), ("max_us", ctypes.c_double),
+                ("wall_s", ctypes.c_double), ("gsamples_per_s", ctypes.c_double),
+                ("mean_batch_requests", ctypes.c_double)]
+
+
+_pdbl = ctypes.POINTER(ctypes.c_double)
+_pi32 = ctypes.POINTER(ctypes.c_int32)
+_SIGS.update({
+    "rng_server_create": (_int, [ctypes.POINTER(rng_server_config_t), ctypes.POINTER(_vp)]),
+    "rng_server_submit": (_int, [_vp, _u64, _u64, _int, _pu64]),
+    "rng_server_poll": (_int, [_vp, _u64, ctypes.POINTER(_int), ctypes.POINTER(_vp)]),
+    "rng_server_release": (_int, [_vp, _u64]),
+    "rng_server_drain": (_int, [_vp]),
+    "rng_server_read_state": (_int, [_vp, _u64, _pu32]),
+    "rng_server_stats": (_int, [_vp, ctypes.POINTER(rng_server_stats_t)]),
+    "rng_server_reset_stats": (_int, [_vp]),
+    "rng_server_replay": (_int, [_vp, _pdbl, _pu64, _pu64, _pi32, _u64, _pu64]),
+    "rng_server_destroy": (_int, [_vp]),
+})
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
     _f.restype = _res
@@ -178,6 +229,128 @@ def rng_generate_split(g, d_state_one, total, n_threads, t, d_out, d_final_state
 def rng_fused_pi(g, d_state, n_streams, n, d_count, stream=None):
     return _check(_lib.rng_fused_pi(g, _ptr(d_state), n_streams, n, _ptr(d_count), _stream(stream)),
                   "rng_fused_pi")
+
+
+def rng_batch_create(max_requests, max_samples):
+    h = ctypes.c_void_p()
+    _check(_lib.rng_batch_create(max_requests, max_samples, ctypes.byref(h)), "rng_batch_create")
+    return h.value
+
+
+def make_requests(reqs):
+    """Build a ctypes array of rng_request_t from (gen, dtype, d_state, state_stride, offset,
+    length, d_out) tuples; device buffers as torch tensors or integer addresses."""
+    arr = (rng_request_t * len(reqs))()
+    for i, (g, t, st, stride, off, n, out) in enumerate(reqs):
+        arr[i] = rng_request_t(g, t, _ptr(st), stride, off, n, _ptr(out))
+    return arr
+
+
+def rng_batch_set(h, reqs, n=None):
+    if not isinstance(reqs, ctypes.Array):
+        reqs = make_requests(reqs)
+    n = len(reqs) if n is None else n
+    return _check(_lib.rng_batch_set(h, reqs, n), "rng_batch_set")
+
+
+def rng_batch_launch(h, stream=None):
+    return _check(_lib.rng_batch_launch(h, _stream(stream)), "rng_batch_launch")
+
+
+def rng_batch_set_shape(h, wg=0, unroll=0, chunk=0):
+    return _check(_lib.rng_batch_set_shape(h, wg, unroll, chunk), "rng_batch_set_shape")
+
+
+def rng_batch_get_shape(h):
+    a, b, c = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+    _check(_lib.rng_batch_get_shape(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "rng_batch_get_shape")
+    return a.value, b.value, c.value
+
+
+def rng_batch_autotune(h, reps=2, stream=None):
+    a, b, c, us = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_float()
+    _check(_lib.rng_batch_autotune(h, reps, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(us),
+                                   _stream(stream)), "rng_batch_autotune")
+    return a.value, b.value, c.value, us.value
+
+
+def rng_batch_destroy(h):
+    return _check(_lib.rng_batch_destroy(h), "rng_batch_destroy")
+
+
+def rng_server_create(n_streams, gens, seed, pool_bytes, max_batch_requests, max_batch_samples,
+                      inflight=3, auto_release=False):
+    cfg = rng_server_config_t()
+    cfg.n_streams = n_streams
+    for i, g in enumerate(gens):
+        cfg.gens[i] = g
+    cfg.n_gens = len(gens)
+    cfg.seed = seed
+    cfg.pool_bytes = pool_bytes
+    cfg.max_batch_requests = max_batch_requests
+    cfg.max_batch_samples = max_batch_samples
+    cfg.inflight = inflight
+    cfg.auto_release = 1 if auto_release else 0
+    h = ctypes.c_void_p()
+    _check(_lib.rng_server_create(ctypes.byref(cfg), ctypes.byref(h)), "rng_server_create")
+    return h.value
+
+
+def rng_server_submit(h, stream_id, length, dtype):
+    t = ctypes.c_uint64()
+    _check(_lib.rng_server_submit(h, stream_id, length, dtype, ctypes.byref(t)), "rng_server_submit")
+    return t.value
+
+
+def rng_server_poll(h, ticket):
+    """(done, device address or None)."""
+    done, ptr = ctypes.c_int(), ctypes.c_void_p()
+    rc = _lib.rng_server_poll(h, ticket, ctypes.byref(done), ctypes.byref(ptr))
+    if rc not in (RNG_OK, RNG_EAGAIN):
+        _check(rc, "rng_server_poll")
+    return bool(done.value), ptr.value
+
+
+def rng_server_release(h, ticket):
+    return _check(_lib.rng_server_release(h, ticket), "rng_server_release")
+
+
+def rng_server_drain(h):
+    return _check(_lib.rng_server_drain(h), "rng_server_drain")
+
+
+def rng_server_read_state(h, stream_id, words):
+    buf = (ctypes.c_uint32 * words)()
+    _check(_lib.rng_server_read_state(h, stream_id, buf), "rng_server_read_state")
+    return list(buf)
+
+
+def rng_server_stats(h):
+    st = rng_server_stats_t()
+    _check(_lib.rng_server_stats(h, ctypes.byref(st)), "rng_server_stats")
+    return {f: getattr(st, f) for f, _ in st._fields_}
+
+
+def rng_server_reset_stats(h):
+    return _check(_lib.rng_server_reset_stats(h), "rng_server_reset_stats")
+
+
+def rng_server_replay(h, t_arrival_s, stream_ids, lengths, dtypes):
+    """Real-time replay of an arrival trace (numpy arrays), then drain; returns tickets."""
+    import numpy as np
+    t = np.ascontiguousarray(t_arrival_s, dtype=np.float64)
+    s = np.ascontiguousarray(stream_ids, dtype=np.uint64)
+    n = np.ascontiguousarray(lengths, dtype=np.uint64)
+    d = np.ascontiguousarray(dtypes, dtype=np.int32)
+    tickets = np.zeros(len(t), dtype=np.uint64)
+    _check(_lib.rng_server_replay(h, t.ctypes.data_as(_pdbl), s.ctypes.data_as(_pu64), n.ctypes.data_as(_pu64),
+                                  d.ctypes.data_as(_pi32), len(t), tickets.ctypes.data_as(_pu64)),
+           "rng_server_replay")
+    return tickets
+
+
+def rng_server_destroy(h):
+    return _check(_lib.rng_server_destroy(h), "rng_server_destroy")
 
 
 def raw():

@@ -2,7 +2,8 @@
 
 Every translation unit under ``csrc/`` is compiled by hipcc in parallel into
 ``_build/`` and linked into ``paper_1101_1846_amd/librng_mi355x.so``.
-Usage: ``python -m paper_1101_1846_amd.build`` (or ``build()`` from Python).
+Usage: ``python paper_1101_1846_amd/build.py`` (run by path: importing the
+package would load the library being rebuilt), or ``__graft_entry__.build()``.
 """
 import concurrent.futures
 import os
@@ -28,7 +29,7 @@ def hipcc():
 
 def flags():
     return [
-        "-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
+        "-O3", "-std=c++20", "-fPIC", "--offload-arch=" + ARCH,
         # packed FP32 instructions are kept out of every kernel
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-I" + INCLUDE, "-I" + CSRC, "-Wall", "-Wno-unused-function",

@@ -1,0 +1,419 @@
+// rng_batch.cpp -- the batched path of the C ABI: plans a batch of
+// independent requests (chunking, grouping by generator and dtype, the
+// doubling-tree work lists), ships the plan through pinned host memory, and
+// replays one captured HIP graph per batch shape: counter reset, root jumps,
+// tree levels, persistent generation kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "rng.h"
+#include "rng_abi_internal.hpp"
+#include "rng_batch_internal.hpp"
+
+namespace rngx {
+int launch_batch_reset(uint32_t *counter, hipStream_t s);
+int launch_batch_root(const BatchArgs &a, uint32_t max_requests, hipStream_t s);
+int launch_batch_level(const BatchArgs &a, uint32_t level, unsigned grid, hipStream_t s);
+int launch_batch_gen(const BatchArgs &a, int wg, int unroll, unsigned grid, hipStream_t s);
+int batch_gen_occupancy(int wg, int unroll, int *blocks_per_cu);
+}  // namespace rngx
+
+using namespace rngx;
+
+struct rng_batch {
+    std::mutex mu;
+    int device = 0;
+    uint32_t max_requests = 0;
+    uint64_t max_samples = 0;
+    uint64_t C = 1024;
+    uint32_t wg = 256, unroll = 8;
+    uint64_t ws_words = 0;
+    BatchHeader *d_hdr = nullptr, *h_hdr = nullptr;
+    BatchReq *d_reqs = nullptr, *h_reqs = nullptr;
+    uint32_t *d_prefix = nullptr, *h_prefix = nullptr;
+    uint32_t *d_ws = nullptr, *d_counter = nullptr;
+    hipEvent_t copied = nullptr;
+    hipStream_t capture = nullptr;  // private stream the graphs are recorded on
+    bool copy_pending = false;
+    bool planned = false;
+    struct Graph {
+        uint32_t levels, wg, unroll;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;
+    int num_cu = 256;
+    std::vector<rng_request_t> last;  // last planned table, re-planned on a chunk change
+};
+
+static uint64_t chunk_capacity(const rng_batch *h, uint64_t C)
+{
+    return (h->max_samples + C - 1) / C + h->max_requests + (uint64_t)kBatchMaxGroups * 64;
+}
+
+static int alloc_ws(rng_batch *h, uint64_t C)
+{
+    uint64_t words = chunk_capacity(h, C) * 8;  // widest state: 8 words
+    if (words <= h->ws_words) return RNG_OK;
+    // the captured graphs hold the old workspace address: drop them
+    for (auto &g : h->graphs) {
+        (void)hipGraphExecDestroy(g.exec);
+        (void)hipGraphDestroy(g.graph);
+    }
+    h->graphs.clear();
+    if (h->d_ws) {
+        (void)hipDeviceSynchronize();  // no launch may still use it
+        (void)hipFree(h->d_ws);
+    }
+    h->d_ws = nullptr;
+    hipError_t e = hipMalloc((void **)&h->d_ws, words * 4);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(batch workspace)");
+    h->ws_words = words;
+    return RNG_OK;
+}
+
+static void free_batch(rng_batch *h)
+{
+    for (auto &g : h->graphs) {
+        (void)hipGraphExecDestroy(g.exec);
+        (void)hipGraphDestroy(g.graph);
+    }
+    if (h->copied) (void)hipEventDestroy(h->copied);
+    if (h->capture) (void)hipStreamDestroy(h->capture);
+    if (h->d_hdr) (void)hipFree(h->d_hdr);
+    if (h->d_reqs) (void)hipFree(h->d_reqs);
+    if (h->d_prefix) (void)hipFree(h->d_prefix);
+    if (h->d_ws) (void)hipFree(h->d_ws);
+    if (h->d_counter) (void)hipFree(h->d_counter);
+    if (h->h_hdr) (void)hipHostFree(h->h_hdr);
+    if (h->h_reqs) (void)hipHostFree(h->h_reqs);
+    if (h->h_prefix) (void)hipHostFree(h->h_prefix);
+    delete h;
+}
+
+static bool shape_ok(uint32_t wg, uint32_t unroll)
+{
+    int b = 0;
+    return batch_gen_occupancy((int)wg, (int)unroll, &b) == 0;
+}
+
+static BatchArgs make_args(rng_batch *h, const DevTables &tab)
+{
+    BatchArgs a{};
+    a.hdr = h->d_hdr;
+    a.reqs = h->d_reqs;
+    a.level_prefix = h->d_prefix;
+    a.max_requests = h->max_requests;
+    a.ws = h->d_ws;
+    a.counter = h->d_counter;
+    a.tab = tab;
+    return a;
+}
+
+static int plan(rng_batch_t *h, const rng_request_t *reqs, uint32_t n);
+
+extern "C" {
+
+int rng_batch_create(uint32_t max_requests, uint64_t max_samples, rng_batch_t **out)
+{
+    if (!out) return fail(RNG_EINVAL, "NULL handle pointer");
+    if (max_requests == 0) return fail(RNG_EINVAL, "max_requests is 0");
+    if (max_samples > ((uint64_t)1 << 40)) return fail(RNG_ERANGE, "max_samples above 2^40");
+    DevTables tab;
+    if (int rc = device_tables(&tab)) return rc;
+    auto *h = new rng_batch();
+    h->max_requests = max_requests;
+    h->max_samples = max_samples;
+    (void)hipGetDevice(&h->device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) h->num_cu = prop.multiProcessorCount;
+    const size_t prefix_words = (size_t)kBatchMaxLevels * (max_requests + 1);
+    hipError_t e = hipSuccess;
+    int rc = RNG_OK;
+    if ((e = hipMalloc((void **)&h->d_hdr, sizeof(BatchHeader))) != hipSuccess ||
+        (e = hipMalloc((void **)&h->d_reqs, sizeof(BatchReq) * max_requests)) != hipSuccess ||
+        (e = hipMalloc((void **)&h->d_prefix, 4 * prefix_words)) != hipSuccess ||
+        (e = hipMalloc((void **)&h->d_counter, 256)) != hipSuccess ||
+        (e = hipHostMalloc((void **)&h->h_hdr, sizeof(BatchHeader), hipHostMallocDefault)) != hipSuccess ||
+        (e = hipHostMalloc((void **)&h->h_reqs, sizeof(BatchReq) * max_requests, hipHostMallocDefault)) != hipSuccess ||
+        (e = hipHostMalloc((void **)&h->h_prefix, 4 * prefix_words, hipHostMallocDefault)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&h->copied, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking)) != hipSuccess)
+        rc = hip_fail(e, "rng_batch_create");
+    if (!rc) rc = alloc_ws(h, h->C);
+    if (rc) {
+        free_batch(h);
+        return rc;
+    }
+    *out = h;
+    return RNG_OK;
+}
+
+int rng_batch_destroy(rng_batch_t *h)
+{
+    if (!h) return RNG_OK;
+    {
+        std::lock_guard<std::mutex> lk(h->mu);
+        if (h->copy_pending) (void)hipEventSynchronize(h->copied);
+    }
+    free_batch(h);
+    return RNG_OK;
+}
+
+int rng_batch_set_shape(rng_batch_t *h, uint32_t wg, uint32_t unroll, uint32_t chunk)
+{
+    if (!h) return fail(RNG_EINVAL, "NULL handle");
+    std::lock_guard<std::mutex> lk(h->mu);
+    uint32_t w = wg ? wg : h->wg, u = unroll ? unroll : h->unroll;
+    if (!shape_ok(w, u)) return fail(RNG_EINVAL, "batch launch shape wg=%u unroll=%u not available", w, u);
+    if (chunk) {
+        if (chunk % kBatchTile) return fail(RNG_EINVAL, "chunk %u is not a multiple of %d", chunk, kBatchTile);
+        if (h->copy_pending) (void)hipEventSynchronize(h->copied);
+        if (int rc = alloc_ws(h, chunk)) return rc;
+        h->C = chunk;
+        h->planned = false;  // the plan depends on the chunk length
+        if (!h->last.empty()) {
+            std::vector<rng_request_t> t = h->last;
+            if (int rc = plan(h, t.data(), (uint32_t)t.size())) return rc;
+        }
+    }
+    h->wg = w;
+    h->unroll = u;
+    return RNG_OK;
+}
+
+int rng_batch_get_shape(rng_batch_t *h, uint32_t *wg, uint32_t *unroll, uint32_t *chunk)
+{
+    if (!h || !wg || !unroll || !chunk) return fail(RNG_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(h->mu);
+    *wg = h->wg;
+    *unroll = h->unroll;
+    *chunk = (uint32_t)h->C;
+    return RNG_OK;
+}
+
+int rng_batch_set(rng_batch_t *h, const rng_request_t *reqs, uint32_t n)
+{
+    if (!h) return fail(RNG_EINVAL, "NULL handle");
+    if (n && !reqs) return fail(RNG_EINVAL, "NULL request table");
+    std::lock_guard<std::mutex> lk(h->mu);
+    int rc = plan(h, reqs, n);
+    if (rc == RNG_OK) h->last.assign(reqs, reqs + n);
+    return rc;
+}
+
+static int plan(rng_batch_t *h, const rng_request_t *reqs, uint32_t n)
+{
+    if (n > h->max_requests) return fail(RNG_ENOMEM, "%u requests > capacity %u", n, h->max_requests);
+    const uint64_t C = h->C;
+    uint64_t total_samples = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        const rng_request_t &r = reqs[i];
+        if (check_gen(r.gen)) return fail(RNG_EINVAL, "request %u: unknown generator %d", i, r.gen);
+        if (r.dtype != RNG_U32 && r.dtype != RNG_F32) return fail(RNG_EINVAL, "request %u: dtype %d", i, r.dtype);
+        if (!r.d_state || ((uintptr_t)r.d_state & 3)) return fail(RNG_EINVAL, "request %u: bad state pointer", i);
+        if (r.state_stride == 0) return fail(RNG_EINVAL, "request %u: state_stride is 0", i);
+        if (r.length && (!r.d_out || ((uintptr_t)r.d_out & 3))) return fail(RNG_EINVAL, "request %u: bad output", i);
+        if (__builtin_add_overflow(total_samples, r.length, &total_samples))
+            return fail(RNG_ERANGE, "total length overflows");
+    }
+    if (total_samples > h->max_samples)
+        return fail(RNG_ENOMEM, "batch of %llu samples > capacity %llu", (unsigned long long)total_samples,
+                    (unsigned long long)h->max_samples);
+    // The pinned staging buffers are about to be rewritten: wait for the
+    // previous launch's copies to leave them.
+    if (h->copy_pending) {
+        hipError_t e = hipEventSynchronize(h->copied);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        h->copy_pending = false;
+    }
+    // group requests by (generator, dtype), stable
+    std::vector<uint32_t> order(n);
+    for (uint32_t i = 0; i < n; ++i) order[i] = i;
+    auto key = [&](uint32_t i) { return reqs[i].gen * 2 + reqs[i].dtype; };
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return key(x) < key(y); });
+
+    BatchHeader &H = *h->h_hdr;
+    std::memset(&H, 0, sizeof(H));
+    H.C = C;
+    H.n = n;
+    uint64_t ws_off = 0, tiles = 0, max_chunks = 0;
+    uint32_t i = 0;
+    while (i < n) {
+        const int k = key(order[i]);
+        BatchGroup &G = H.groups[H.ngroups];
+        G.gen = (uint32_t)reqs[order[i]].gen;
+        G.dtype = (uint32_t)reqs[order[i]].dtype;
+        G.words = (uint32_t)gen_words(reqs[order[i]].gen);
+        G.req_begin = i;
+        uint64_t chunks = 0;
+        for (; i < n && key(order[i]) == k; ++i) {
+            const rng_request_t &r = reqs[order[i]];
+            BatchReq &q = h->h_reqs[i];
+            q.state = r.d_state;
+            q.stride = r.state_stride;
+            q.offset = r.offset;
+            q.length = r.length;
+            q.out = (uint32_t *)r.d_out;
+            q.chunk_base = (uint32_t)chunks;
+            q.nchunks = (uint32_t)((r.length + C - 1) / C);
+            q.group = H.ngroups;
+            q.pad = 0;
+            chunks += q.nchunks;
+            max_chunks = std::max<uint64_t>(max_chunks, q.nchunks);
+        }
+        G.req_end = i;
+        G.nchunks = (uint32_t)chunks;
+        G.nchunks_pad = (uint32_t)((chunks + 63) / 64 * 64);
+        G.tile_begin = (uint32_t)tiles;
+        tiles += G.nchunks_pad / 64;
+        G.tile_end = (uint32_t)tiles;
+        G.ws_off = ws_off;
+        ws_off += (uint64_t)G.words * G.nchunks_pad;
+        H.ngroups++;
+    }
+    if (ws_off > h->ws_words) return fail(RNG_ENOMEM, "batch needs %llu workspace words > %llu",
+                                          (unsigned long long)ws_off, (unsigned long long)h->ws_words);
+    H.n_tiles = (uint32_t)tiles;
+    uint32_t levels = 0;
+    while (((uint64_t)1 << levels) < max_chunks) ++levels;
+    if (levels > (uint32_t)kBatchMaxLevels) return fail(RNG_ERANGE, "a request needs more than 2^40 chunks");
+    H.levels = levels;
+    const uint32_t stride = h->max_requests + 1;
+    for (uint32_t l = 0; l < levels; ++l) {
+        uint32_t *pre = h->h_prefix + (size_t)l * stride;
+        const uint64_t lo = (uint64_t)1 << l;
+        uint64_t acc = 0;
+        for (uint32_t r = 0; r < n; ++r) {
+            pre[r] = (uint32_t)acc;
+            const uint64_t nc = h->h_reqs[r].nchunks;
+            if (nc > lo) acc += std::min(nc, 2 * lo) - lo;
+        }
+        pre[n] = (uint32_t)acc;
+        H.level_total[l] = (uint32_t)acc;
+    }
+    h->planned = true;
+    return RNG_OK;
+}
+
+int rng_batch_launch(rng_batch_t *h, void *stream)
+{
+    if (!h) return fail(RNG_EINVAL, "NULL handle");
+    std::lock_guard<std::mutex> lk(h->mu);
+    if (!h->planned) return fail(RNG_EINVAL, "rng_batch_set has not been called since the last shape change");
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (dev != h->device) return fail(RNG_EINVAL, "batch created on device %d, current device %d", h->device, dev);
+    DevTables tab;
+    if (int rc = device_tables(&tab)) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const BatchHeader &H = *h->h_hdr;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(h->d_hdr, h->h_hdr, sizeof(BatchHeader), hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (H.n && (e = hipMemcpyAsync(h->d_reqs, h->h_reqs, sizeof(BatchReq) * H.n, hipMemcpyHostToDevice, st)) !=
+                    hipSuccess) ||
+        (H.levels && (e = hipMemcpyAsync(h->d_prefix, h->h_prefix, 4ull * H.levels * (h->max_requests + 1),
+                                         hipMemcpyHostToDevice, st)) != hipSuccess))
+        return hip_fail(e, "rng_batch_launch: upload");
+    if ((e = hipEventRecord(h->copied, st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    h->copy_pending = true;
+
+    rng_batch::Graph *gp = nullptr;
+    for (auto &g : h->graphs)
+        if (g.levels == H.levels && g.wg == h->wg && g.unroll == h->unroll) gp = &g;
+    if (!gp) {
+        int per_cu = 0;
+        if (batch_gen_occupancy((int)h->wg, (int)h->unroll, &per_cu) || per_cu <= 0) per_cu = 1;
+        const unsigned gen_grid = (unsigned)(h->num_cu * per_cu);
+        const uint64_t cap = chunk_capacity(h, h->C);
+        const unsigned level_grid = (unsigned)std::min<uint64_t>((cap + 255) / 256, 4096);
+        const BatchArgs a = make_args(h, tab);
+        rng_batch::Graph g{H.levels, h->wg, h->unroll, nullptr, nullptr};
+        // Recorded on the handle's own stream (the caller's may be the null
+        // stream, which cannot capture); nothing runs while recording.
+        hipStream_t cs = h->capture;
+        if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return hip_fail(e, "hipStreamBeginCapture");
+        int rc = launch_batch_reset(h->d_counter, cs);
+        if (!rc) rc = launch_batch_root(a, h->max_requests, cs);
+        for (uint32_t l = 0; !rc && l < H.levels; ++l) rc = launch_batch_level(a, l, level_grid, cs);
+        if (!rc) rc = launch_batch_gen(a, (int)h->wg, (int)h->unroll, gen_grid, cs);
+        e = hipStreamEndCapture(cs, &g.graph);
+        if (rc) {
+            if (g.graph) (void)hipGraphDestroy(g.graph);
+            return check_launch(rc, "rng_batch_launch: capture");
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        if ((e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0)) != hipSuccess) {
+            (void)hipGraphDestroy(g.graph);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        h->graphs.push_back(g);
+        gp = &h->graphs.back();
+    }
+    if ((e = hipGraphLaunch(gp->exec, st)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return RNG_OK;
+}
+
+int rng_batch_autotune(rng_batch_t *h, uint32_t reps, uint32_t *best_wg, uint32_t *best_unroll,
+                       uint32_t *best_chunk, float *best_us, void *stream)
+{
+    if (!h || !best_wg || !best_unroll || !best_chunk) return fail(RNG_EINVAL, "NULL argument");
+    if (reps == 0) return fail(RNG_EINVAL, "reps is 0");
+    {
+        std::lock_guard<std::mutex> lk(h->mu);
+        if (h->last.empty()) return fail(RNG_EINVAL, "no planned batch to tune on");
+    }
+    static const uint32_t shapes[][2] = {{64, 8}, {128, 8}, {256, 8}, {512, 8}, {256, 1}, {256, 2}, {256, 4}, {256, 16}};
+    static const uint32_t chunks[] = {512, 1024, 2048, 4096};
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    hipError_t e;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(e, "hipEventCreate");
+    }
+    float best = 1e30f;
+    uint32_t bw = h->wg, bu = h->unroll, bc = (uint32_t)h->C;
+    int rc = RNG_OK;
+    for (uint32_t c : chunks) {
+        for (auto &sh : shapes) {
+            if ((rc = rng_batch_set_shape(h, sh[0], sh[1], c))) break;
+            if ((rc = rng_batch_launch(h, stream))) break;  // warm-up (and graph capture)
+            (void)hipEventRecord(e0, st);
+            for (uint32_t r = 0; r < reps && !rc; ++r) rc = rng_batch_launch(h, stream);
+            (void)hipEventRecord(e1, st);
+            if (rc) break;
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+                rc = hip_fail(e, "hipEventSynchronize");
+                break;
+            }
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            float us = ms * 1000.0f / reps;
+            if (us < best) {
+                best = us;
+                bw = sh[0];
+                bu = sh[1];
+                bc = c;
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if ((rc = rng_batch_set_shape(h, bw, bu, bc))) return rc;
+    *best_wg = bw;
+    *best_unroll = bu;
+    *best_chunk = bc;
+    if (best_us) *best_us = best;
+    return RNG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,227 @@
+"""Batched path: every request of a batch equals the slice
+[offset, offset + length) of its stream's serial sequence (the oracle), its
+state ends advanced by offset + length, and results are the same alone and in
+the mix, for every launch shape, chunk length and graph replay."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+GENS = ["MWC32", "XS256", "XS32", "KISS", "MWC1616"]
+
+
+@pytest.fixture(scope="module")
+def rng():
+    import paper_1101_1846_amd as R
+    R.rng_init()
+    return R
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available()
+    return T
+
+
+def _u32(t):
+    import torch as T
+    T.cuda.synchronize()
+    return t.cpu().numpy().view(np.uint32)
+
+
+class Mix:
+    """A random request mix over per-generator state pools [words][n_g]."""
+
+    def __init__(self, rng, torch, oracle, n, seed, max_len, misalign=True, offsets=True, gens=GENS):
+        r = np.random.default_rng(seed)
+        self.R, self.T, self.O = rng, torch, oracle
+        self.gen = [gens[i] for i in r.integers(0, len(gens), n)]
+        self.dtype = r.integers(0, 2, n)
+        self.length = r.integers(0, max_len + 1, n)
+        self.length[r.random(n) < 0.1] = 0
+        self.offset = np.where(r.random(n) < 0.3, r.integers(0, 10 ** 6, n), 0) if offsets else np.zeros(n, int)
+        if offsets:
+            self.offset[r.random(n) < 0.05] = (1 << 40) + 3
+        counts = {g: self.gen.count(g) for g in gens}
+        self.pool, self.idx = {}, []
+        seen = {g: 0 for g in gens}
+        for g in self.gen:
+            self.idx.append(seen[g])
+            seen[g] += 1
+        for g in gens:
+            if counts[g]:
+                gid = rng.GENERATORS[g]
+                st = torch.empty((rng.rng_state_words(gid), counts[g]), dtype=torch.int32, device="cuda")
+                rng.rng_seed(gid, 40 + gid, 0, counts[g], st)
+                self.pool[g] = st
+        self.seed_of = {g: 40 + rng.GENERATORS[g] for g in gens}
+        self.counts = counts
+        self.offs = []
+        pos = 0
+        for i in range(n):
+            pos = (pos + 3) // 4 * 4 + (int(r.integers(0, 4)) if misalign else 0)
+            self.offs.append(pos)
+            pos += int(self.length[i])
+        self.out = torch.zeros(pos + 8, dtype=torch.int32, device="cuda")
+
+    def requests(self, subset=None):
+        R = self.R
+        reqs = []
+        for i in (range(len(self.gen)) if subset is None else subset):
+            g = self.gen[i]
+            pool = self.pool[g]
+            base = pool.data_ptr() + 4 * self.idx[i]
+            reqs.append((R.GENERATORS[g], int(self.dtype[i]), base, self.counts[g], int(self.offset[i]),
+                         int(self.length[i]), self.out.data_ptr() + 4 * self.offs[i]))
+        return reqs
+
+    def expected(self, i, pass_no=1):
+        """Oracle output of request i on its `pass_no`-th run from the seeded pool."""
+        O, g = self.O, self.gen[i]
+        o = O.GENERATORS[g]
+        st = O.seed(o, self.seed_of[g], 1, first_stream=self.idx[i])
+        out = None
+        for _ in range(pass_no):
+            if self.offset[i]:
+                O.skip(o, st, int(self.offset[i]))
+            out = O.generate(o, st, int(self.length[i]), int(self.dtype[i]))[0]
+        return out.view(np.uint32), st[:, 0]
+
+    def check(self, subset=None, pass_no=1):
+        got = _u32(self.out)
+        pools = {g: _u32(p) for g, p in self.pool.items()}
+        for i in (range(len(self.gen)) if subset is None else subset):
+            exp, st = self.expected(i, pass_no)
+            n = int(self.length[i])
+            assert np.array_equal(got[self.offs[i]:self.offs[i] + n], exp), (i, self.gen[i], n)
+            assert np.array_equal(pools[self.gen[i]][:, self.idx[i]], st), (i, "state")
+
+
+def test_batch_mixed_requests(rng, torch, oracle):
+    m = Mix(rng, torch, oracle, 300, seed=1, max_len=20000)
+    h = rng.rng_batch_create(1000, 1 << 24)
+    try:
+        rng.rng_batch_set(h, m.requests())
+        rng.rng_batch_launch(h)
+        m.check()
+    finally:
+        rng.rng_batch_destroy(h)
+
+
+def test_batch_alone_equals_in_mix(rng, torch, oracle):
+    mix = Mix(rng, torch, oracle, 120, seed=2, max_len=9000)
+    alone = Mix(rng, torch, oracle, 120, seed=2, max_len=9000)
+    h = rng.rng_batch_create(200, 1 << 22)
+    try:
+        rng.rng_batch_set(h, mix.requests())
+        rng.rng_batch_launch(h)
+        for i in (0, 7, 33, 119):
+            rng.rng_batch_set(h, alone.requests([i]))
+            rng.rng_batch_launch(h)
+        torch.cuda.synchronize()
+        a, b = _u32(mix.out), _u32(alone.out)
+        for i in (0, 7, 33, 119):
+            n = int(mix.length[i])
+            assert np.array_equal(a[mix.offs[i]:mix.offs[i] + n], b[alone.offs[i]:alone.offs[i] + n])
+        alone.check([0, 7, 33, 119])
+    finally:
+        rng.rng_batch_destroy(h)
+
+
+@pytest.mark.parametrize("shape", [(64, 8), (128, 8), (256, 8), (512, 8), (256, 1), (256, 2), (256, 4),
+                                   (256, 16)])
+def test_batch_every_shape(rng, torch, oracle, shape):
+    m = Mix(rng, torch, oracle, 80, seed=3, max_len=6000)
+    h = rng.rng_batch_create(100, 1 << 20)
+    try:
+        rng.rng_batch_set_shape(h, shape[0], shape[1], 0)
+        assert rng.rng_batch_get_shape(h)[:2] == shape
+        rng.rng_batch_set(h, m.requests())
+        rng.rng_batch_launch(h)
+        m.check()
+    finally:
+        rng.rng_batch_destroy(h)
+
+
+@pytest.mark.parametrize("chunk", [64, 192, 1024, 4096])
+def test_batch_chunk_lengths(rng, torch, oracle, chunk):
+    m = Mix(rng, torch, oracle, 60, seed=4, max_len=30000)
+    h = rng.rng_batch_create(100, 1 << 22)
+    try:
+        rng.rng_batch_set_shape(h, 0, 0, chunk)
+        rng.rng_batch_set(h, m.requests())
+        rng.rng_batch_launch(h)
+        m.check()
+    finally:
+        rng.rng_batch_destroy(h)
+
+
+def test_batch_graph_replays(rng, torch, oracle):
+    """The same plan launched three times, with eager library work and a
+    synchronisation between replays: replay k must give pass k of every stream."""
+    m = Mix(rng, torch, oracle, 50, seed=5, max_len=5000, offsets=False)
+    h = rng.rng_batch_create(64, 1 << 20)
+    side = torch.empty((1, 4096), dtype=torch.int32, device="cuda")
+    side_out = torch.empty(4096 * 64, dtype=torch.int32, device="cuda")
+    try:
+        rng.rng_batch_set(h, m.requests())
+        for k in (1, 2, 3):
+            rng.rng_batch_launch(h)
+            torch.cuda.synchronize()
+            m.check(pass_no=k)
+            rng.rng_seed(rng.RNG_XS32, 9, 0, 4096, side)
+            rng.rng_generate(rng.RNG_XS32, side, 4096, 64, 0, side_out)
+            torch.cuda.synchronize()
+            rng.rng_batch_set(h, m.requests())
+    finally:
+        rng.rng_batch_destroy(h)
+
+
+def test_batch_validation(rng, torch):
+    h = rng.rng_batch_create(4, 1000)
+    st = torch.empty(8, dtype=torch.int32, device="cuda")
+    out = torch.empty(2000, dtype=torch.int32, device="cuda")
+    try:
+        import ctypes
+        L = rng.raw()
+        bad = [
+            [(99, 0, st, 1, 0, 10, out)],
+            [(rng.RNG_XS32, 5, st, 1, 0, 10, out)],
+            [(rng.RNG_XS32, 0, 0, 1, 0, 10, out)],
+            [(rng.RNG_XS32, 0, st, 0, 0, 10, out)],
+            [(rng.RNG_XS32, 0, st, 1, 0, 10, out.data_ptr() + 2)],
+        ]
+        for b in bad:
+            arr = rng.make_requests(b)
+            assert L.rng_batch_set(h, arr, 1) == rng.RNG_EINVAL
+        too_many = rng.make_requests([(rng.RNG_XS32, 0, st, 1, 0, 1, out)] * 5)
+        assert L.rng_batch_set(h, too_many, 5) == rng.RNG_ENOMEM
+        too_long = rng.make_requests([(rng.RNG_XS32, 0, st, 1, 0, 1001, out)])
+        assert L.rng_batch_set(h, too_long, 1) == rng.RNG_ENOMEM
+        assert L.rng_batch_set_shape(h, 96, 8, 0) == rng.RNG_EINVAL
+        assert L.rng_batch_set_shape(h, 256, 8, 100) == rng.RNG_EINVAL
+        del ctypes
+    finally:
+        rng.rng_batch_destroy(h)
+
+
+def test_batch_empty_and_skip_only(rng, torch, oracle):
+    """A batch of zero-length requests only advances the states by their offsets."""
+    st = torch.empty((8, 3), dtype=torch.int32, device="cuda")
+    rng.rng_seed(rng.RNG_XS256, 11, 0, 3, st)
+    h = rng.rng_batch_create(8, 100)
+    try:
+        reqs = [(rng.RNG_XS256, 0, st.data_ptr() + 4 * i, 3, 1000 * (i + 1), 0, 0) for i in range(3)]
+        rng.rng_batch_set(h, reqs)
+        rng.rng_batch_launch(h)
+        ref = oracle.seed(oracle.XS256, 11, 3)
+        for i in range(3):
+            col = np.ascontiguousarray(ref[:, i:i + 1])
+            oracle.skip(oracle.XS256, col, 1000 * (i + 1))
+            assert np.array_equal(_u32(st)[:, i], col[:, 0])
+        rng.rng_batch_set(h, [])
+        rng.rng_batch_launch(h)
+        torch.cuda.synchronize()
+    finally:
+        rng.rng_batch_destroy(h)

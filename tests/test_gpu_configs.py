@@ -123,3 +123,44 @@ def test_autotune_keeps_values(rng, torch, oracle):
     ref = oracle.generate(oracle.XS32, oracle.seed(oracle.XS32, 5, S), N)
     assert np.array_equal(_u32(out).reshape(S, N), ref)
     rng.rng_set_shape(g, rng.RNG_U32, *old)
+
+
+def test_batched_10k_requests(rng, torch, oracle):
+    """The batched workload (10^4 requests, MWC32/XS256/KISS, u32/f32 50/50,
+    length log-uniform in [2^8, 2^22]) after autotuning the shape as bench.py
+    does: 200 sampled requests plus the 5 longest and 5 shortest, every sample
+    and final state."""
+    import bench
+    from paper_1101_1846_amd import workloads as W
+    tab = W.batch_table(10000, seed=4)
+    names = tab["generators"]
+    offs, words = W.layout_outputs(tab["length"])
+    out = torch.empty(words, dtype=torch.int32, device="cuda")
+    total = int(tab["length"].sum())
+    h = rng.rng_batch_create(10000, total)
+    try:
+        pools, where = bench.batch_pools(torch, rng, "cuda", tab)
+        reqs = [(rng.GENERATORS[names[g]], int(d), p, s, 0, int(n), out.data_ptr() + 4 * int(o))
+                for g, d, (p, s, _), n, o in zip(tab["gen"], tab["dtype"], where, tab["length"], offs)]
+        rng.rng_batch_set(h, reqs)
+        rng.rng_batch_autotune(h, reps=1)
+        pools, where = bench.batch_pools(torch, rng, "cuda", tab)  # fresh states
+        reqs = [(rng.GENERATORS[names[g]], int(d), p, s, 0, int(n), out.data_ptr() + 4 * int(o))
+                for g, d, (p, s, _), n, o in zip(tab["gen"], tab["dtype"], where, tab["length"], offs)]
+        rng.rng_batch_set(h, reqs)
+        rng.rng_batch_launch(h)
+        torch.cuda.synchronize()
+        order = np.argsort(tab["length"])
+        pick = set(np.random.default_rng(1).choice(len(reqs), 200, replace=False).tolist())
+        pick |= set(order[:5].tolist()) | set(order[-5:].tolist())
+        host_pools = {g: _u32(p) for g, p in pools.items()}
+        for i in sorted(pick):
+            g = names[tab["gen"][i]]
+            o = oracle.GENERATORS[g]
+            st = oracle.seed(o, 5, 1, first_stream=where[i][2])
+            ref = oracle.generate(o, st, int(tab["length"][i]), int(tab["dtype"][i]))[0].view(np.uint32)
+            got = _u32(out[int(offs[i]):int(offs[i]) + int(tab["length"][i])])
+            assert np.array_equal(got, ref), (i, g)
+            assert np.array_equal(host_pools[g][:, where[i][2]], st[:, 0]), (i, "state")
+    finally:
+        rng.rng_batch_destroy(h)

@@ -1,0 +1,126 @@
+"""Served path: requests replayed in real time through the continuous-batching
+server.  Every result must be the next slice of its stream's serial sequence
+(requests on one stream in arrival order), whatever shared its batch, and the
+resident states must end advanced by everything served."""
+import ctypes
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+KINDS = ["MWC32", "XS256", "KISS"]
+
+
+@pytest.fixture(scope="module")
+def rng():
+    import paper_1101_1846_amd as R
+    R.rng_init()
+    return R
+
+
+@pytest.fixture(scope="module")
+def hip():
+    import torch
+    assert torch.cuda.is_available()
+    lib = ctypes.CDLL("libamdhip64.so")
+    lib.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    lib.hipMemcpy.restype = ctypes.c_int
+    return lib
+
+
+def _read(hip, ptr, n):
+    buf = np.empty(n, dtype=np.uint32)
+    assert hip.hipMemcpy(buf.ctypes.data, ptr, 4 * n, 2) == 0  # device to host
+    return buf
+
+
+def _expected_per_stream(oracle, n_streams, seed, streams, lengths):
+    """Serial uint32 sequence of every stream over the concatenation of its
+    requests, and its final state."""
+    seq, fin = {}, {}
+    for s in range(n_streams):
+        k = s % len(KINDS)
+        o = oracle.GENERATORS[KINDS[k]]
+        st = oracle.seed(o, seed + k, 1, first_stream=s // len(KINDS))
+        total = int(lengths[streams == s].sum())
+        seq[s] = oracle.generate(o, st, total)[0] if total else np.zeros(0, np.uint32)
+        fin[s] = st[:, 0]
+    return seq, fin
+
+
+def test_server_results_are_ordered_stream_slices(rng, hip, oracle):
+    from paper_1101_1846_amd import workloads as W
+    n_streams, seed, n = 30, 8, 1500
+    gens = [rng.GENERATORS[k] for k in KINDS]
+    h = rng.rng_server_create(n_streams, gens, seed, 1 << 30, 512, 1 << 22, inflight=3, auto_release=False)
+    try:
+        r = np.random.default_rng(12)
+        t = W.poisson_arrivals(50_000, n, seed=13)
+        streams = r.integers(0, n_streams, n)
+        lengths = W.log_uniform_lengths(r, n, 4, 13)
+        dtypes = r.integers(0, 2, n)
+        tickets = rng.rng_server_replay(h, t, streams, lengths, dtypes)
+        st = rng.rng_server_stats(h)
+        assert st["completed"] == n and st["batches"] >= 1
+        assert 0 < st["p50_us"] <= st["p99_us"] <= st["max_us"]
+        seq, fin = _expected_per_stream(oracle, n_streams, seed, streams, lengths)
+        pos = {s: 0 for s in range(n_streams)}
+        for i, tk in enumerate(tickets):
+            done, ptr = rng.rng_server_poll(h, int(tk))
+            assert done and ptr
+            s, L = int(streams[i]), int(lengths[i])
+            exp = seq[s][pos[s]:pos[s] + L]
+            if dtypes[i]:
+                exp = oracle.to_f32(exp).view(np.uint32)
+            assert np.array_equal(_read(hip, ptr, L), exp), (i, s)
+            pos[s] += L
+            rng.rng_server_release(h, int(tk))
+        for s in range(n_streams):
+            words = rng.rng_state_words(rng.GENERATORS[KINDS[s % 3]])
+            assert np.array_equal(np.array(rng.rng_server_read_state(h, s, words), np.uint32), fin[s])
+    finally:
+        rng.rng_server_destroy(h)
+
+
+def test_server_admission_under_memory_pressure(rng, oracle):
+    """A 320 KiB output pool and a burst of 400 requests of up to 256 KiB: admission
+    waits for released memory, every request completes, and the states end as
+    the oracle's after the per-stream totals."""
+    from paper_1101_1846_amd import workloads as W
+    n_streams, seed, n = 24, 3, 400
+    gens = [rng.GENERATORS[k] for k in KINDS]
+    h = rng.rng_server_create(n_streams, gens, seed, 320 << 10, 64, 1 << 16, inflight=3, auto_release=True)
+    try:
+        r = np.random.default_rng(5)
+        streams = r.integers(0, n_streams, n)
+        lengths = W.log_uniform_lengths(r, n, 6, 16)
+        rng.rng_server_replay(h, np.zeros(n), streams, lengths, r.integers(0, 2, n))
+        st = rng.rng_server_stats(h)
+        assert st["completed"] == n
+        assert st["admission_waits"] > 0
+        _, fin = _expected_per_stream(oracle, n_streams, seed, streams, lengths)
+        for s in range(n_streams):
+            words = rng.rng_state_words(rng.GENERATORS[KINDS[s % 3]])
+            assert np.array_equal(np.array(rng.rng_server_read_state(h, s, words), np.uint32), fin[s])
+    finally:
+        rng.rng_server_destroy(h)
+
+
+def test_server_argument_errors(rng):
+    gens = [rng.GENERATORS[k] for k in KINDS]
+    h = rng.rng_server_create(9, gens, 1, 1 << 20, 16, 1 << 12, inflight=1)
+    try:
+        L = rng.raw()
+        t = ctypes.c_uint64()
+        assert L.rng_server_submit(h, 9, 10, 0, ctypes.byref(t)) == rng.RNG_ERANGE
+        assert L.rng_server_submit(h, 0, 0, 0, ctypes.byref(t)) == rng.RNG_ERANGE
+        assert L.rng_server_submit(h, 0, (1 << 12) + 1, 0, ctypes.byref(t)) == rng.RNG_ERANGE
+        assert L.rng_server_submit(h, 0, 10, 3, ctypes.byref(t)) == rng.RNG_EINVAL
+        d, p = ctypes.c_int(), ctypes.c_void_p()
+        assert L.rng_server_poll(h, 12345, ctypes.byref(d), ctypes.byref(p)) == rng.RNG_EINVAL
+        tk = rng.rng_server_submit(h, 4, 100, 1)
+        rng.rng_server_drain(h)
+        assert rng.rng_server_poll(h, tk)[0]
+    finally:
+        rng.rng_server_destroy(h)
