@@ -24,7 +24,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0           # MI355X HBM3E, 8 TB/s
-VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9  # int32 lane-ops/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+# 32-bit integer VALU issues at the FP32-vector rate: 157.3 TFLOP/s counts an
+# FMA as 2 operations, so 78.6e12 lane-operations/s (256 CUs x 2.4 GHz x 128).
+VALU_PEAK_OPS = 157.3e12 / 2
+FUSED_OPS_PER_SAMPLE = 24
+FUSED_VALU_PER_SAMPLE = 21.5     # 172 VALU instructions per 8 samples in the compiled loop
 
 S_BULK, N_BULK = 1 << 20, 256
 STEP_GENS = ["XS256", "XS32", "KISS"]
@@ -246,14 +250,34 @@ def _time(torch, fn, reps):
 
 
 def side_workloads(torch, R, dev, stream, only=None):
+    """Every workload besides the timed step, or only the one named."""
+    parts = {"small": small_workloads, "split": split_workload}
     res = {}
+    if only in parts:
+        res.update(parts[only](torch, R, dev))
+        return res
     if only == "batched":
         res["batched_10k_requests"] = batched_workload(torch, R, dev)
+        return res
+    if only == "fused":
+        res.update(fused_workload(torch, R, dev))
         return res
     if only == "served":
         res["served"] = served_workload(R, batched_workload(torch, R, dev)["single_large_call_GSamples_s"])
         return res
-    # MWC32, 4096 streams x 1024 (small, launch-bound; chunked by jump-ahead)
+    res.update(small_workloads(torch, R, dev))
+    res.update(split_workload(torch, R, dev))
+    res["batched_10k_requests"] = batched_workload(torch, R, dev)
+    res["served"] = served_workload(R, res["batched_10k_requests"]["single_large_call_GSamples_s"])
+    res.update(fused_workload(torch, R, dev))
+    torch.cuda.empty_cache()
+    return res
+
+
+def small_workloads(torch, R, dev):
+    """MWC32 4096 streams x 1024 (launch-bound; chunked by jump-ahead) and the
+    MWC1616 / MWC32 store mode at the bulk size."""
+    res = {}
     g = R.RNG_MWC32
     S, N = 4096, 1024
     st = torch.empty((2, S), dtype=torch.int32, device=dev)
@@ -262,7 +286,6 @@ def side_workloads(torch, R, dev, stream, only=None):
     ms = _time(torch, lambda: R.rng_generate(g, st, S, N, R.RNG_U32, o), 200)
     res["mwc32_4096x1024"] = {"us_per_call": round(ms * 1e3, 2),
                               "GSamples_s": round(S * N / (ms * 1e-3) / 1e9, 1)}
-    # MWC1616 and MWC32 at the bulk size
     for name in ("MWC1616", "MWC32"):
         g = R.GENERATORS[name]
         st = torch.empty((R.rng_state_words(g), S_BULK), dtype=torch.int32, device=dev)
@@ -273,7 +296,12 @@ def side_workloads(torch, R, dev, stream, only=None):
             res["%s_bulk_%s" % (name, dname)] = {"ms": round(ms, 4),
                                                   "GSamples_s": round(S_BULK * N_BULK / (ms * 1e-3) / 1e9, 1)}
         del o
-    # jump-ahead split of one 2^30-sample sequence over 2^20 threads
+    return res
+
+
+def split_workload(torch, R, dev):
+    """Jump-ahead split of one 2^30-sample sequence over 2^20 threads."""
+    res = {}
     total, T = 1 << 30, 1 << 20
     o = torch.empty(total, dtype=torch.int32, device=dev)
     for name in ("MWC32", "XS256"):
@@ -289,16 +317,32 @@ def side_workloads(torch, R, dev, stream, only=None):
                                        "GSamples_s": round(total / (ms * 1e-3) / 1e9, 1),
                                        "GB_s": round(4 * total / (ms * 1e-3) / 1e9, 1)}
     del o
-    res["batched_10k_requests"] = batched_workload(torch, R, dev)
-    res["served"] = served_workload(R, res["batched_10k_requests"]["single_large_call_GSamples_s"])
-    # fused pi over 2^34 KISS samples (no stores: integer-VALU bound)
+    return res
+
+
+def fused_workload(torch, R, dev):
+    """Fused consumer over 2^34 KISS samples (no stores: integer-VALU bound)."""
+    res = {}
     g = R.RNG_KISS
     S, N = 1 << 20, 1 << 14
     st = torch.empty((6, S), dtype=torch.int32, device=dev)
     R.rng_seed(g, 6, 0, S, st)
     cnt = torch.zeros(1, dtype=torch.int64, device=dev)
     ms = _time(torch, lambda: R.rng_fused_pi(g, st, S, N, cnt), 5)
-    res["fused_pi_kiss_2^34"] = {"ms": round(ms, 3), "GSamples_s": round(S * N / (ms * 1e-3) / 1e9, 1)}
+    rate = S * N / (ms * 1e-3)
+    calib = {name: R.rng_calibrate_valu(op) for op, name in enumerate(("add_xor", "mad_u24", "mul_lo"))}
+    res["fused_pi_kiss_2^34"] = {
+        "ms": round(ms, 3), "GSamples_s": round(rate / 1e9, 1),
+        # abstract operations per sample (eq. (9)): KISS 20 (MWC1616 10, xorshift32 6, LCG 2, combine 2)
+        # + 4 per sample for the pair test (shift, square, add, compare, count)
+        "roofline": {"kernel": "k_fused_pi<KISS>", "bound": "alu", "unit": "Gop/s",
+                     "achieved": round(rate * FUSED_OPS_PER_SAMPLE / 1e9, 1),
+                     "peak": round(VALU_PEAK_OPS / 1e9, 1),
+                     "frac": round(rate * FUSED_OPS_PER_SAMPLE / VALU_PEAK_OPS, 4),
+                     "ops_per_sample": FUSED_OPS_PER_SAMPLE,
+                     "valu_instructions_per_sample": FUSED_VALU_PER_SAMPLE,
+                     "valu_lane_instructions_per_s": round(rate * FUSED_VALU_PER_SAMPLE / 1e9, 1),
+                     "measured_valu_peak_lane_ops_per_s": {k: round(v / 1e9, 1) for k, v in calib.items()}}}
     torch.cuda.empty_cache()
     return res
 

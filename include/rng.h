@@ -116,6 +116,12 @@ int rng_autotune(int g, int t, uint64_t n_streams, uint64_t n, uint32_t *d_state
                  void *d_out_scratch, uint32_t reps, uint32_t *best_wg, uint32_t *best_unroll,
                  float *best_us, void *stream);
 
+/* Measured 32-bit integer VALU rate of the current device in lane-operations
+ * per second, for op 0 (add + xor), 1 (24-bit multiply-add), 2 (32-bit
+ * multiply low): eight independent chains per lane on every SIMD.  The
+ * paper measured its achievable peaks the same way (Sec. V).  Synchronous. */
+int rng_calibrate_valu(int op, double *lane_ops_per_s, void *stream);
+
 /* Advance every stream by k steps without producing output: sequence
  * splitting needs the i-th number without the intermediate ones (Sec.
  * II.A.4).  MWC: z <- a^k z mod (a*b - 1) with z = c*b + x; XorShift: the

@@ -52,6 +52,7 @@ _SIGS = {
     "rng_split_workspace_bytes": (_int, [_int, _u64, _pu64]),
     "rng_generate_split": (_int, [_int, _vp, _u64, _u64, _int, _vp, _vp, _vp, _u64, _vp]),
     "rng_fused_pi": (_int, [_int, _vp, _u64, _u64, _vp, _vp]),
+    "rng_calibrate_valu": (_int, [_int, ctypes.POINTER(ctypes.c_double), _vp]),
 }
 
 
@@ -229,6 +230,12 @@ def rng_generate_split(g, d_state_one, total, n_threads, t, d_out, d_final_state
 def rng_fused_pi(g, d_state, n_streams, n, d_count, stream=None):
     return _check(_lib.rng_fused_pi(g, _ptr(d_state), n_streams, n, _ptr(d_count), _stream(stream)),
                   "rng_fused_pi")
+
+
+def rng_calibrate_valu(op, stream=None):
+    v = ctypes.c_double()
+    _check(_lib.rng_calibrate_valu(op, ctypes.byref(v), _stream(stream)), "rng_calibrate_valu")
+    return v.value
 
 
 def rng_batch_create(max_requests, max_samples):
