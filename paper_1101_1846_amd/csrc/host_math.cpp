@@ -216,7 +216,22 @@ static HostTables *build_tables()
         *M = (*M) * (*M);
     }
     delete M;
+    T->xs256_t4.resize((size_t)kPowBits * 8192);
+    for (int b = 0; b < kPowBits; ++b) xs256_nibble_table(&T->xs256_pow[(size_t)b * 2048], &T->xs256_t4[(size_t)b * 8192]);
     return T;
+}
+
+void xs256_nibble_table(const uint32_t *cols, uint32_t *t4)
+{
+    for (int p = 0; p < 64; ++p)
+        for (int h = 0; h < 2; ++h)
+            for (int v = 0; v < 16; ++v)
+                for (int w = 0; w < 4; ++w) {
+                    uint32_t x = 0;
+                    for (int k = 0; k < 4; ++k)
+                        if ((v >> k) & 1) x ^= cols[(4 * p + k) * 8 + 4 * h + w];
+                    t4[((p * 2 + h) * 16 + v) * 4 + w] = x;
+                }
 }
 
 const HostTables &host_tables()

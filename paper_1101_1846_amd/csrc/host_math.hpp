@@ -48,7 +48,14 @@ struct HostTables {
     uint32_t xs32_pow[kPowBits][32];           // M^(2^b), 32 columns
     uint32_t mwc16_pow_fold[kMwc16Count][kPowBits];  // a_i^(2^b) * 2^48 mod m_i
     std::vector<uint32_t> xs256_pow;           // [64][256][8]: M^(2^b)
+    std::vector<uint32_t> xs256_t4;            // [64][64][2][16][4]: 4-bit lookup tables of M^(2^b)
 };
+
+// 4-bit lookup table of a 256x256 GF(2) matrix given by its 256 columns of 8
+// words: entry (p, h, v) holds words 4h .. 4h+3 of the XOR of the columns 4p+k
+// over the set bits k of v (p < 64, h < 2, v < 16; 32 KiB).  M x is then the
+// XOR over p of entries (p, 0, v_p) and (p, 1, v_p), v_p the p-th nibble of x.
+void xs256_nibble_table(const uint32_t *cols, uint32_t *t4);
 const HostTables &host_tables();
 
 // Fold-domain constants for an arbitrary jump distance (used by the host for

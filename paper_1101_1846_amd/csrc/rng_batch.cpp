@@ -34,8 +34,9 @@ struct rng_batch {
     uint64_t ws_words = 0;
     BatchHeader *d_hdr = nullptr, *h_hdr = nullptr;
     BatchReq *d_reqs = nullptr, *h_reqs = nullptr;
-    uint32_t *d_prefix = nullptr, *h_prefix = nullptr;
-    uint32_t *d_ws = nullptr, *d_counter = nullptr;
+    uint32_t *d_lvl = nullptr, *h_lvl = nullptr;  // [2 * seg_cap] segments, then block starts
+    uint64_t lvl_words = 0;
+    uint32_t *d_ws = nullptr, *d_counter = nullptr, *d_map = nullptr;
     hipEvent_t copied = nullptr;
     hipStream_t capture = nullptr;  // private stream the graphs are recorded on
     bool copy_pending = false;
@@ -48,6 +49,7 @@ struct rng_batch {
     std::vector<Graph> graphs;
     int num_cu = 256;
     std::vector<rng_request_t> last;  // last planned table, re-planned on a chunk change
+    uint32_t n_seg = 0, n_blk = 0;    // level segments and block starts of the current plan
 };
 
 static uint64_t chunk_capacity(const rng_batch *h, uint64_t C)
@@ -55,24 +57,47 @@ static uint64_t chunk_capacity(const rng_batch *h, uint64_t C)
     return (h->max_samples + C - 1) / C + h->max_requests + (uint64_t)kBatchMaxGroups * 64;
 }
 
+// Segments of all levels: at most one per request and level.
+static uint64_t seg_capacity(const rng_batch *h) { return (uint64_t)kBatchMaxLevels * h->max_requests; }
+
+// Block starts of all levels: the levels' work items sum to fewer than the
+// chunks, so sum(ceil(items / 256)) <= chunks / 256 + levels.
+static uint64_t lvl_capacity(const rng_batch *h, uint64_t C)
+{
+    return 2 * seg_capacity(h) + chunk_capacity(h, C) / 256 + kBatchMaxLevels + 1;
+}
+
+// Sizes the chunk workspace, the chunk-to-request map and the level work
+// lists for chunk length C.  Growing any of them drops the captured graphs,
+// which hold the old addresses.
 static int alloc_ws(rng_batch *h, uint64_t C)
 {
-    uint64_t words = chunk_capacity(h, C) * 8;  // widest state: 8 words
-    if (words <= h->ws_words) return RNG_OK;
-    // the captured graphs hold the old workspace address: drop them
+    const uint64_t chunks = chunk_capacity(h, C);
+    const uint64_t words = chunks * 8;  // widest state: 8 words
+    const uint64_t lvl = lvl_capacity(h, C);
+    if (words <= h->ws_words && lvl <= h->lvl_words) return RNG_OK;
+    if (chunks >= ((uint64_t)1 << 32)) return fail(RNG_ENOMEM, "more than 2^32 chunks of %llu samples",
+                                                   (unsigned long long)C);
     for (auto &g : h->graphs) {
         (void)hipGraphExecDestroy(g.exec);
         (void)hipGraphDestroy(g.graph);
     }
     h->graphs.clear();
-    if (h->d_ws) {
-        (void)hipDeviceSynchronize();  // no launch may still use it
-        (void)hipFree(h->d_ws);
-    }
-    h->d_ws = nullptr;
-    hipError_t e = hipMalloc((void **)&h->d_ws, words * 4);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc(batch workspace)");
+    (void)hipDeviceSynchronize();  // no launch may still use the old buffers
+    if (h->d_ws) (void)hipFree(h->d_ws);
+    if (h->d_map) (void)hipFree(h->d_map);
+    if (h->d_lvl) (void)hipFree(h->d_lvl);
+    if (h->h_lvl) (void)hipHostFree(h->h_lvl);
+    h->d_ws = h->d_map = h->d_lvl = h->h_lvl = nullptr;
+    h->ws_words = h->lvl_words = 0;
+    hipError_t e;
+    if ((e = hipMalloc((void **)&h->d_ws, words * 4)) != hipSuccess) return hip_fail(e, "hipMalloc(batch workspace)");
+    if ((e = hipMalloc((void **)&h->d_map, chunks * 4)) != hipSuccess) return hip_fail(e, "hipMalloc(chunk map)");
+    if ((e = hipMalloc((void **)&h->d_lvl, lvl * 4)) != hipSuccess) return hip_fail(e, "hipMalloc(level lists)");
+    if ((e = hipHostMalloc((void **)&h->h_lvl, lvl * 4, hipHostMallocDefault)) != hipSuccess)
+        return hip_fail(e, "hipHostMalloc(level lists)");
     h->ws_words = words;
+    h->lvl_words = lvl;
     return RNG_OK;
 }
 
@@ -86,12 +111,13 @@ static void free_batch(rng_batch *h)
     if (h->capture) (void)hipStreamDestroy(h->capture);
     if (h->d_hdr) (void)hipFree(h->d_hdr);
     if (h->d_reqs) (void)hipFree(h->d_reqs);
-    if (h->d_prefix) (void)hipFree(h->d_prefix);
+    if (h->d_lvl) (void)hipFree(h->d_lvl);
+    if (h->d_map) (void)hipFree(h->d_map);
     if (h->d_ws) (void)hipFree(h->d_ws);
     if (h->d_counter) (void)hipFree(h->d_counter);
     if (h->h_hdr) (void)hipHostFree(h->h_hdr);
     if (h->h_reqs) (void)hipHostFree(h->h_reqs);
-    if (h->h_prefix) (void)hipHostFree(h->h_prefix);
+    if (h->h_lvl) (void)hipHostFree(h->h_lvl);
     delete h;
 }
 
@@ -106,8 +132,9 @@ static BatchArgs make_args(rng_batch *h, const DevTables &tab)
     BatchArgs a{};
     a.hdr = h->d_hdr;
     a.reqs = h->d_reqs;
-    a.level_prefix = h->d_prefix;
-    a.max_requests = h->max_requests;
+    a.seg = (const uint2 *)h->d_lvl;
+    a.blk_first = h->d_lvl + 2 * seg_capacity(h);
+    a.chunk_req = h->d_map;
     a.ws = h->d_ws;
     a.counter = h->d_counter;
     a.tab = tab;
@@ -131,16 +158,13 @@ int rng_batch_create(uint32_t max_requests, uint64_t max_samples, rng_batch_t **
     (void)hipGetDevice(&h->device);
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) h->num_cu = prop.multiProcessorCount;
-    const size_t prefix_words = (size_t)kBatchMaxLevels * (max_requests + 1);
     hipError_t e = hipSuccess;
     int rc = RNG_OK;
     if ((e = hipMalloc((void **)&h->d_hdr, sizeof(BatchHeader))) != hipSuccess ||
         (e = hipMalloc((void **)&h->d_reqs, sizeof(BatchReq) * max_requests)) != hipSuccess ||
-        (e = hipMalloc((void **)&h->d_prefix, 4 * prefix_words)) != hipSuccess ||
         (e = hipMalloc((void **)&h->d_counter, 256)) != hipSuccess ||
         (e = hipHostMalloc((void **)&h->h_hdr, sizeof(BatchHeader), hipHostMallocDefault)) != hipSuccess ||
         (e = hipHostMalloc((void **)&h->h_reqs, sizeof(BatchReq) * max_requests, hipHostMallocDefault)) != hipSuccess ||
-        (e = hipHostMalloc((void **)&h->h_prefix, 4 * prefix_words, hipHostMallocDefault)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&h->copied, hipEventDisableTiming)) != hipSuccess ||
         (e = hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking)) != hipSuccess)
         rc = hip_fail(e, "rng_batch_create");
@@ -283,19 +307,36 @@ static int plan(rng_batch_t *h, const rng_request_t *reqs, uint32_t n)
     while (((uint64_t)1 << levels) < max_chunks) ++levels;
     if (levels > (uint32_t)kBatchMaxLevels) return fail(RNG_ERANGE, "a request needs more than 2^40 chunks");
     H.levels = levels;
-    const uint32_t stride = h->max_requests + 1;
+    for (uint32_t g = 0; g < H.ngroups; ++g) H.has_xs256 |= H.groups[g].gen == (uint32_t)RNG_XS256;
+    uint2 *segs = (uint2 *)h->h_lvl;
+    uint32_t *blks = h->h_lvl + 2 * seg_capacity(h);
+    const bool pow2 = (C & (C - 1)) == 0;
+    const uint32_t lc = (uint32_t)__builtin_ctzll(C);
+    uint32_t S = 0, B = 0;
     for (uint32_t l = 0; l < levels; ++l) {
-        uint32_t *pre = h->h_prefix + (size_t)l * stride;
+        LevelInfo &L = H.lvl[l];
+        L.seg_off = S;
+        L.blk_off = B;
+        L.pow = pow2 && lc + l < 64 ? lc + l : 0xFFFFFFFFu;
         const uint64_t lo = (uint64_t)1 << l;
         uint64_t acc = 0;
         for (uint32_t r = 0; r < n; ++r) {
-            pre[r] = (uint32_t)acc;
             const uint64_t nc = h->h_reqs[r].nchunks;
-            if (nc > lo) acc += std::min(nc, 2 * lo) - lo;
+            if (nc <= lo) continue;
+            segs[S++] = make_uint2(r, (uint32_t)acc);
+            acc += std::min(nc, 2 * lo) - lo;
         }
-        pre[n] = (uint32_t)acc;
+        L.seg_n = S - L.seg_off;
         H.level_total[l] = (uint32_t)acc;
+        uint32_t k = 0;
+        for (uint64_t t0 = 0; t0 < acc; t0 += 256) {
+            while (k + 1 < L.seg_n && segs[L.seg_off + k + 1].y <= t0) ++k;
+            blks[B++] = k;
+        }
     }
+    H.pad = 0;
+    h->n_seg = S;
+    h->n_blk = B;
     h->planned = true;
     return RNG_OK;
 }
@@ -316,8 +357,10 @@ int rng_batch_launch(rng_batch_t *h, void *stream)
     if ((e = hipMemcpyAsync(h->d_hdr, h->h_hdr, sizeof(BatchHeader), hipMemcpyHostToDevice, st)) != hipSuccess ||
         (H.n && (e = hipMemcpyAsync(h->d_reqs, h->h_reqs, sizeof(BatchReq) * H.n, hipMemcpyHostToDevice, st)) !=
                     hipSuccess) ||
-        (H.levels && (e = hipMemcpyAsync(h->d_prefix, h->h_prefix, 4ull * H.levels * (h->max_requests + 1),
-                                         hipMemcpyHostToDevice, st)) != hipSuccess))
+        (h->n_seg && (e = hipMemcpyAsync(h->d_lvl, h->h_lvl, 8ull * h->n_seg, hipMemcpyHostToDevice, st)) !=
+                         hipSuccess) ||
+        (h->n_blk && (e = hipMemcpyAsync(h->d_lvl + 2 * seg_capacity(h), h->h_lvl + 2 * seg_capacity(h),
+                                         4ull * h->n_blk, hipMemcpyHostToDevice, st)) != hipSuccess))
         return hip_fail(e, "rng_batch_launch: upload");
     if ((e = hipEventRecord(h->copied, st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     h->copy_pending = true;
@@ -330,7 +373,7 @@ int rng_batch_launch(rng_batch_t *h, void *stream)
         if (batch_gen_occupancy((int)h->wg, (int)h->unroll, &per_cu) || per_cu <= 0) per_cu = 1;
         const unsigned gen_grid = (unsigned)(h->num_cu * per_cu);
         const uint64_t cap = chunk_capacity(h, h->C);
-        const unsigned level_grid = (unsigned)std::min<uint64_t>((cap + 255) / 256, 4096);
+        const unsigned level_grid = (unsigned)std::min<uint64_t>((cap + 255) / 256, 1024);
         const BatchArgs a = make_args(h, tab);
         rng_batch::Graph g{H.levels, h->wg, h->unroll, nullptr, nullptr};
         // Recorded on the handle's own stream (the caller's may be the null

@@ -38,6 +38,19 @@ struct BatchGroup {
     uint64_t ws_off;              // word offset of the group's [words][nchunks_pad] states
 };
 
+// Work list of one tree level.  Level l derives chunk j in [2^l, 2^(l+1)) of
+// every request with more than 2^l chunks from its chunk j - 2^l; those
+// requests are the level's segments, in table order, each with the exclusive
+// prefix of the work items before it.  Items are handled in blocks of 256;
+// the block start table gives the segment holding each block's first item,
+// so that a block needs only its 256 following segments.
+struct LevelInfo {
+    uint32_t seg_off;  // first segment of the level in the segment array
+    uint32_t seg_n;    // segments (requests with more than 2^l chunks)
+    uint32_t blk_off;  // first entry of the level in the block start array
+    uint32_t pow;      // b with C * 2^l = 2^b, or 0xFFFFFFFF when C is no power of two
+};
+
 // Per-batch header, rewritten before every launch (the captured graph only
 // holds pointers to it).
 struct BatchHeader {
@@ -46,17 +59,21 @@ struct BatchHeader {
     uint32_t ngroups;
     uint32_t n_tiles;
     uint32_t levels;      // doubling-tree levels used
+    uint32_t has_xs256;   // some group is XS256 (its level tables are staged in LDS)
+    uint32_t pad;
     uint32_t level_total[kBatchMaxLevels];  // work items per level
+    LevelInfo lvl[kBatchMaxLevels];
     BatchGroup groups[kBatchMaxGroups];
 };
 
 struct BatchArgs {
     const BatchHeader *hdr;
-    const BatchReq *reqs;          // [n], sorted by group
-    const uint32_t *level_prefix;  // [levels][n + 1] exclusive prefix of per-request work per level
-    uint32_t max_requests;         // row stride of level_prefix is max_requests + 1
-    uint32_t *ws;                  // chunk-state workspace
-    uint32_t *counter;             // [0] tile counter of the persistent kernel
+    const BatchReq *reqs;         // [n], sorted by group
+    const uint2 *seg;             // level segments: (sorted request index, exclusive item prefix)
+    const uint32_t *blk_first;    // per level and 256-item block: segment (within the level) of its first item
+    uint32_t *chunk_req;          // [64 * n_tiles] sorted request index of every chunk (padded group order)
+    uint32_t *ws;                 // chunk-state workspace
+    uint32_t *counter;            // [0] tile counter of the persistent kernel
     DevTables tab;
 };
 

@@ -47,6 +47,7 @@ __global__ __launch_bounds__(256) void k_batch_root(BatchArgs a)
         const BatchReq q = a.reqs[r];
         const BatchGroup &gr = h.groups[q.group];
         uint32_t *qs = q.state;
+        if (q.nchunks) a.chunk_req[gr.tile_begin * 64 + q.chunk_base] = r;
         with_gen(gr.gen, [&]<class G>() {
             G g;
             g.load(qs, q.stride, 0, a.tab);
@@ -57,31 +58,60 @@ __global__ __launch_bounds__(256) void k_batch_root(BatchArgs a)
     }
 }
 
-// Level i of the doubling tree: chunk j in [2^i, min(2^(i+1), nchunks)) of
-// every request starts where chunk j - 2^i starts, jumped by C * 2^i.
+// Level l of the doubling tree: chunk j in [2^l, min(2^(l+1), nchunks)) of
+// every request starts where chunk j - 2^l starts, jumped by C * 2^l.  A
+// block takes 256 consecutive work items: it loads the 256 segments from its
+// first item's segment on (a block spans at most 256 of them) into LDS, and
+// every thread finds its request there.  XS256 jumps by a power of two read
+// that power's lookup table, staged in LDS once per block.
 __global__ __launch_bounds__(256) void k_batch_level(BatchArgs a, uint32_t level)
 {
+    __shared__ uint4 s_t4[2048];
+    __shared__ uint32_t s_pre[256], s_req[256];
     const BatchHeader &h = *a.hdr;
     if (level >= h.levels) return;
+    const LevelInfo L = h.lvl[level];
     const uint32_t total = h.level_total[level];
-    const uint32_t *pre = a.level_prefix + (uint64_t)level * (a.max_requests + 1);
-    const uint64_t lo = (uint64_t)1 << level;
+    const uint32_t nblk = (total + 255) / 256;
+    if (blockIdx.x >= nblk) return;
+    const bool staged = h.has_xs256 && L.pow < 64;
+    if (staged) stage_t4(s_t4, a.tab.xs256_t4 + (size_t)L.pow * 2048);
+    const uint32_t lo = 1u << level;
     const uint64_t dist = h.C << level;
-    for (uint32_t t = blockIdx.x * 256 + threadIdx.x; t < total; t += gridDim.x * 256) {
-        uint32_t L = 0, R = h.n;  // largest r with pre[r] <= t
-        while (R - L > 1) {
-            uint32_t m = (L + R) >> 1;
-            if (pre[m] <= t) L = m; else R = m;
+    for (uint32_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const uint32_t k = a.blk_first[L.blk_off + blk] + threadIdx.x;
+        __syncthreads();  // the previous block's segments are consumed (and the table is staged)
+        if (k < L.seg_n) {
+            const uint2 sg = a.seg[L.seg_off + k];
+            s_req[threadIdx.x] = sg.x;
+            s_pre[threadIdx.x] = sg.y;
+        } else {
+            s_req[threadIdx.x] = 0;
+            s_pre[threadIdx.x] = 0xFFFFFFFFu;
         }
-        const BatchReq q = a.reqs[L];
+        __syncthreads();
+        const uint32_t t = blk * 256 + threadIdx.x;
+        if (t >= total) continue;
+        uint32_t i = 0;  // largest i with s_pre[i] <= t (s_pre[0] <= t by construction)
+#pragma unroll
+        for (uint32_t step = 128; step; step >>= 1)
+            if (s_pre[i + step] <= t) i += step;
+        const uint32_t r = s_req[i];
+        const BatchReq q = a.reqs[r];
         const BatchGroup &gr = h.groups[q.group];
-        const uint64_t j = lo + (t - pre[L]);
-        const uint32_t c = q.chunk_base + (uint32_t)j;
+        const uint32_t c = q.chunk_base + lo + (t - s_pre[i]);
+        a.chunk_req[gr.tile_begin * 64 + c] = r;
+        uint32_t *ws = a.ws + gr.ws_off;
         with_gen(gr.gen, [&]<class G>() {
             G g;
-            g.load(a.ws + gr.ws_off, gr.nchunks_pad, c - lo, a.tab);
-            g.jump(dist, a.tab);
-            g.store(a.ws + gr.ws_off, gr.nchunks_pad, c);
+            g.load(ws, gr.nchunks_pad, c - lo, a.tab);
+            if constexpr (G::kId == G_XS256) {
+                if (staged) g.jump_table(s_t4);
+                else g.jump(dist, a.tab);
+            } else {
+                g.jump(dist, a.tab);
+            }
+            g.store(ws, gr.nchunks_pad, c);
         });
     }
 }
@@ -106,12 +136,7 @@ __device__ void batch_tile(const BatchArgs &a, const BatchGroup &gr, uint32_t ti
     const uint32_t c0 = (tile - gr.tile_begin) * 64;
     const bool active = c0 + lane < gr.nchunks;
     const uint32_t c = active ? c0 + lane : c0;
-    uint32_t L = gr.req_begin, R = gr.req_end;  // request holding chunk c
-    while (R - L > 1) {
-        uint32_t m = (L + R) >> 1;
-        if (a.reqs[m].chunk_base <= c) L = m; else R = m;
-    }
-    const BatchReq q = a.reqs[L];
+    const BatchReq q = a.reqs[a.chunk_req[gr.tile_begin * 64 + c]];  // written by the root and tree kernels
     const uint64_t j = c - q.chunk_base;
     const uint64_t start = j * h.C;
     const uint32_t len = active ? (uint32_t)min<uint64_t>(h.C, q.length - start) : 0;

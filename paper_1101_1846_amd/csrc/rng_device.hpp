@@ -22,7 +22,7 @@ struct DevTables {
     const uint32_t *lcg_pow;       // [64][2] (A, C) of 2^b LCG steps
     const uint32_t *xs32_pow;      // [64][32] columns of M^(2^b)
     const uint32_t *mwc16_pow;     // [392][64] a_i^(2^b) * 2^48 mod m_i
-    const uint32_t *xs256_pow;     // [64][256][8] columns of M^(2^b)
+    const uint4 *xs256_t4;         // [64][64][2][16] 4-bit lookup tables of M^(2^b)
     uint32_t mwc32_a;              // 65274
     uint64_t mwc32_m;              // a * 2^32 - 1
 };
@@ -119,28 +119,39 @@ __device__ __forceinline__ uint32_t gf2_apply32(const uint32_t *__restrict__ col
     return r;
 }
 
-// v <- M v for the 256x256 matrix of the r = 8 XorShift, 256 columns of 8
-// words.  Every lane of a wave reads the same column, so the matrix streams
-// through the scalar cache.  Kept out of line: one copy serves every kernel
-// that jumps.
-struct V8 {
-    uint32_t v[8];
-};
-
-__device__ __noinline__ V8 gf2_apply256(const uint32_t *__restrict__ col, V8 in)
+// x <- M x for a 256x256 GF(2) matrix M given by its 4-bit lookup table T
+// (2048 quads, 32 KiB): quads (2p + h) * 16 + v hold words 4h .. 4h+3 of the
+// XOR of columns 4p + k over the set bits k of v.  The product is the XOR of
+// the two quads selected by each of the 64 nibbles of x: 128 independent
+// 16-byte lookups instead of 256 masked column XORs.  T may sit in LDS (a
+// staged table) or in global memory; inlined, the loads take that space.
+__device__ __forceinline__ void gf2_apply256_t4(const uint4 *T, uint32_t (&x)[8])
 {
-    V8 r = {{0, 0, 0, 0, 0, 0, 0, 0}};
+    uint32_t r[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-    for (int w = 0; w < 8; ++w) {
-#pragma unroll
-        for (int b = 0; b < 32; ++b) {
-            uint32_t mask = (uint32_t)__builtin_amdgcn_sbfe((int)in.v[w], b, 1);
-            const uint32_t *c = col + (32 * w + b) * 8;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) r.v[i] ^= c[i] & mask;
-        }
+    for (int p = 0; p < 64; p += 2) {
+        const uint32_t n0 = (x[p >> 3] >> (4 * (p & 7))) & 15u;
+        const uint32_t n1 = (x[p >> 3] >> (4 * (p & 7) + 4)) & 15u;
+        const uint4 a0 = T[(2 * p) * 16 + n0], a1 = T[(2 * p + 1) * 16 + n0];
+        const uint4 b0 = T[(2 * p + 2) * 16 + n1], b1 = T[(2 * p + 3) * 16 + n1];
+        r[0] = xor3(r[0], a0.x, b0.x);
+        r[1] = xor3(r[1], a0.y, b0.y);
+        r[2] = xor3(r[2], a0.z, b0.z);
+        r[3] = xor3(r[3], a0.w, b0.w);
+        r[4] = xor3(r[4], a1.x, b1.x);
+        r[5] = xor3(r[5], a1.y, b1.y);
+        r[6] = xor3(r[6], a1.z, b1.z);
+        r[7] = xor3(r[7], a1.w, b1.w);
     }
-    return r;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[i] = r[i];
+}
+
+// Copies one 32 KiB lookup table into LDS with the whole workgroup (the
+// caller synchronises before use).
+__device__ __forceinline__ void stage_t4(uint4 *lds, const uint4 *T)
+{
+    for (uint32_t i = threadIdx.x; i < 2048; i += blockDim.x) lds[i] = T[i];
 }
 
 // ---------------------------------------------------------------- generators
@@ -218,14 +229,11 @@ struct GenXS256 {
     }
     __device__ void jump(uint64_t k, const DevTables &tab)
     {
-        V8 x;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) x.v[i] = v[i];
         for (int b = 0; b < 64 && (k >> b); ++b)
-            if ((k >> b) & 1) x = gf2_apply256(tab.xs256_pow + (size_t)b * 2048, x);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] = x.v[i];
+            if ((k >> b) & 1) gf2_apply256_t4(tab.xs256_t4 + (size_t)b * 2048, v);
     }
+    // One jump by the power of two whose lookup table T holds (staged in LDS).
+    __device__ __forceinline__ void jump_table(const uint4 *T) { gf2_apply256_t4(T, v); }
     __device__ void seed(const uint64_t *d, const DevTables &)
     {
         uint32_t any = 0;

@@ -54,16 +54,35 @@ __global__ __launch_bounds__(256) void k_skip(uint32_t *__restrict__ st, uint64_
 
 // One level of the doubling tree used by sequence splitting: thread t in
 // [lo, min(2 lo, T)) starts where thread t - lo starts plus dist samples.
+// For XS256 with a power-of-two distance, each workgroup first stages that
+// power's 32 KiB lookup table in LDS; the grid then strides over the level.
 template <class G>
 __global__ __launch_bounds__(256) void k_tree_level(uint32_t *__restrict__ ws, uint64_t T, uint64_t lo,
                                                     uint64_t dist, DevTables tab)
 {
-    uint64_t t = lo + (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= T || t >= 2 * lo) return;
-    G g;
-    g.load(ws, T, t - lo, tab);
-    g.jump(dist, tab);
-    g.store(ws, T, t);
+    const uint64_t n = min(lo, T - lo);
+    if constexpr (G::kId == G_XS256) {
+        __shared__ uint4 s_t4[2048];
+        const bool staged = (dist & (dist - 1)) == 0;
+        if (staged) {
+            stage_t4(s_t4, tab.xs256_t4 + (size_t)__builtin_ctzll(dist) * 2048);
+            __syncthreads();
+        }
+        for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+            G g;
+            g.load(ws, T, i, tab);
+            if (staged) g.jump_table(s_t4);
+            else g.jump(dist, tab);
+            g.store(ws, T, lo + i);
+        }
+    } else {
+        for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+            G g;
+            g.load(ws, T, i, tab);
+            g.jump(dist, tab);
+            g.store(ws, T, lo + i);
+        }
+    }
 }
 
 // ------------------------------------------------------------------ tile store
@@ -366,8 +385,11 @@ template <class G>
 int launch_tree_level_t(uint32_t *ws, uint64_t T, uint64_t lo, uint64_t dist, const DevTables &tab,
                         hipStream_t stream)
 {
-    uint64_t n = min(lo, T - lo);
-    hipLaunchKernelGGL(k_tree_level<G>, dim3(grid_for(n, 256)), dim3(256), 0, stream, ws, T, lo, dist, tab);
+    // XS256 workgroups each stage a 32 KiB table: at most 2 per CU, striding
+    const uint64_t n = min(lo, T - lo);
+    const unsigned cap = G::kId == G_XS256 ? 512 : 8192, blocks = grid_for(n, 256);
+    hipLaunchKernelGGL(k_tree_level<G>, dim3(blocks < cap ? blocks : cap), dim3(256), 0, stream, ws, T, lo, dist,
+                       tab);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
