@@ -170,3 +170,24 @@ def test_fused_pi_parity(rng, torch, oracle, name, S, N):
     torch.cuda.synchronize()
     assert int(cnt.item()) == ref
     assert np.array_equal(_host(st), ref_st)
+
+
+# Large grids of whole 64-stream groups with one chunk per stream: 4101 groups
+# (more than the device holds at once), one tile per stream (N = 64), 32-deep
+# tiles (N = 96 with 1024-lane workgroups), and the smallest stream count that
+# still takes one chunk per stream (65600 > 2^16).
+PERSIST = [(262464, 192, None), (262464, 64, None), (262464, 96, (1024, 4)), (65600, 128, (64, 16))]
+
+
+@pytest.mark.parametrize("name", GENS)
+@pytest.mark.parametrize("dt", ["u32", "f32"])
+@pytest.mark.parametrize("S,N,shape", PERSIST)
+def test_large_grid_parity(rng, torch, oracle, name, dt, S, N, shape):
+    g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
+    t = rng.DTYPES[dt]
+    st = _dev_state(torch, rng, g, 9, S)
+    out = _gen(torch, rng, g, st, S, N, t, shape=shape)
+    ref_st = oracle.seed(o, 9, S)
+    ref = oracle.generate(o, ref_st, N, t, threads=16)
+    assert np.array_equal(out.view(np.uint32), ref.view(np.uint32))
+    assert np.array_equal(_host(st), ref_st)
