@@ -23,6 +23,13 @@ constexpr int kGenTile = RNGX_GEN_TILE;
 #endif
 constexpr int kStoreMode = RNGX_STORE_MODE;
 
+// Resident schedule for one-chunk launches of whole stream groups: a wave
+// preloads the states of up to kResidentGroups groups before its first store.
+#ifndef RNGX_RESIDENT_GROUPS
+#define RNGX_RESIDENT_GROUPS 8
+#endif
+constexpr int kResidentGroups = RNGX_RESIDENT_GROUPS;
+
 struct GenArgs {
     uint32_t *state;  // [W][ld]
     uint64_t ld;      // state word stride (>= S)
@@ -32,6 +39,7 @@ struct GenArgs {
     uint32_t P;       // chunks per stream
     uint32_t vec4;    // rows 16-byte aligned: 128-bit stores
     uint32_t nt;      // non-temporal store hint
+    uint32_t resident; // waves stride over 64-stream groups with preloaded states (set by the launcher)
     DevTables tab;
 };
 

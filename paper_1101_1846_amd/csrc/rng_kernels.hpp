@@ -179,6 +179,71 @@ __device__ __forceinline__ void gen_to_row(G &g, uint32_t *row, int k)
     }
 }
 
+// Resident form of the pipelined schedule, for launches with one chunk per
+// stream, whole 64-stream groups and N a multiple of K.  The grid holds the
+// waves that fit on the device; wave w takes groups w, w + W, w + 2W, ... (at
+// most kResidentGroups).  It loads all their states first and waits for them
+// once, before its first store, then only writes: the vector memory counter
+// retires loads and stores in issue order, so any later wait for a load
+// would also wait for every store still in flight.  The store pipeline runs
+// across group boundaries, and the states move down a register queue.
+template <class G, int DT, int U, int K>
+__device__ __forceinline__ void gen_resident(const GenArgs &a, uint32_t *tile, int lane, uint64_t wave,
+                                             uint64_t nwaves)
+{
+    constexpr int LD = K + 4, QPR = K / 4, RPI = 64 / QPR, MG = kResidentGroups;
+    const int r0 = lane / QPR, q = lane % QPR;
+    const uint32_t *src = tile + r0 * LD + 4 * q;
+    uint32_t *row = tile + lane * LD;
+    const uint64_t N = a.N, groups = a.S / 64;
+    if (wave >= groups) return;
+    const uint32_t ng = (uint32_t)((groups - wave + nwaves - 1) / nwaves);
+    const uint32_t T = (uint32_t)(N / K);
+    uint32_t *out = (uint32_t *)a.out;
+    G gs[MG];
+#pragma unroll
+    for (int i = 0; i < MG; ++i)
+        if ((uint32_t)i < ng) gs[i].load(a.state, a.ld, (wave + (uint64_t)i * nwaves) * 64 + lane, a.tab);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): every state is in before the first store
+    G g = gs[0];
+    uint64_t sb = wave;
+    u32x4 P[QPR];
+#pragma unroll
+    for (int k = 0; k < K; k += U) gen_to_row<G, DT, U>(g, row, k);
+    RNGX_COMPILER_FENCE();
+#pragma unroll
+    for (int i = 0; i < QPR; ++i) P[i] = *(const u32x4 *)(src + i * RPI * LD);
+    RNGX_COMPILER_FENCE();
+    uint32_t *pdst = out + (sb * 64 + r0) * N + 4 * q;
+    uint32_t t = 1;
+    for (uint32_t gi = 0;;) {
+        for (; t < T; ++t) {
+#pragma unroll
+            for (int k = 0; k < K; k += U) {
+                gen_to_row<G, DT, U>(g, row, k);
+#pragma unroll
+                for (int i = k * QPR / K; i < (k + U) * QPR / K; ++i)
+                    *(u32x4 *)(pdst + (uint64_t)(i * RPI) * N) = P[i];
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            RNGX_COMPILER_FENCE();
+#pragma unroll
+            for (int i = 0; i < QPR; ++i) P[i] = *(const u32x4 *)(src + i * RPI * LD);
+            RNGX_COMPILER_FENCE();
+            pdst = out + (sb * 64 + r0) * N + (uint64_t)t * K + 4 * q;
+        }
+        g.store(a.state, a.ld, sb * 64 + lane);
+        if (++gi == ng) break;
+        sb += nwaves;
+#pragma unroll
+        for (int i = 0; i + 1 < MG; ++i) gs[i] = gs[i + 1];
+        g = gs[0];
+        t = 0;
+    }
+#pragma unroll
+    for (int i = 0; i < QPR; ++i) *(u32x4 *)(pdst + (uint64_t)(i * RPI) * N) = P[i];
+}
+
 template <class G, int DT, int WG, int U, int K, int kMode>
 __global__ __launch_bounds__(WG) void k_generate(GenArgs a)
 {
@@ -191,6 +256,12 @@ __global__ __launch_bounds__(WG) void k_generate(GenArgs a)
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t wave = (uint64_t)blockIdx.x * NW + wv;
+    if constexpr (kMode == 2) {
+        if (a.resident) {
+            gen_resident<G, DT, U, K>(a, &lds[wv * 64 * LD], lane, wave, (uint64_t)gridDim.x * NW);
+            return;
+        }
+    }
     const uint64_t sb = wave / a.P, j = wave - sb * a.P;
     const uint64_t s0 = sb * 64;
     if (s0 >= a.S) return;
@@ -410,7 +481,28 @@ int launch_generate_shape(const GenArgs &a, hipStream_t stream)
     // 160 KiB of LDS, then 32 (chunk lengths are multiples of kGenTile, so
     // of both depths)
     constexpr int K = (WG * (kGenTile + 4) * 4 <= 160 * 1024) ? kGenTile : 32;
-    hipLaunchKernelGGL((k_generate<G, DT, WG, U, K, kMode>), dim3((unsigned)blocks), dim3(WG), 0, stream, a);
+    GenArgs b = a;
+    b.resident = 0;
+    if constexpr (kMode == 2) {
+        if (a.P == 1 && a.vec4 && a.S % 64 == 0 && a.N % K == 0) {
+            // the workgroups resident at once; each wave then takes at most
+            // kResidentGroups groups
+            static const uint64_t resident = [] {
+                int per_cu = 0, dev = 0, cus = 0;
+                if (hipGetDevice(&dev) != hipSuccess ||
+                    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+                    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_generate<G, DT, WG, U, K, kMode>, WG, 0) !=
+                        hipSuccess)
+                    return (uint64_t)0;
+                return (uint64_t)per_cu * (uint64_t)cus;
+            }();
+            if (resident && blocks <= resident * kResidentGroups) {
+                b.resident = 1;
+                if (blocks > resident) blocks = resident;
+            }
+        }
+    }
+    hipLaunchKernelGGL((k_generate<G, DT, WG, U, K, kMode>), dim3((unsigned)blocks), dim3(WG), 0, stream, b);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
