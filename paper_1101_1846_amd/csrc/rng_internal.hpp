@@ -11,11 +11,14 @@ namespace rngx {
 enum { RNG_DT_U32 = 0, RNG_DT_F32 = 1 };
 
 // Samples each lane produces into its LDS tile between two transposed
-// stores (the tile is [64][kGenTile + 4] words per wavefront).
+// stores (the tile is [64][depth + 4] words per wavefront).  Workgroups whose
+// tiles would not fit in the 160 KiB of LDS take 32.
 #ifndef RNGX_GEN_TILE
-#define RNGX_GEN_TILE 64
+#define RNGX_GEN_TILE 128
 #endif
 constexpr int kGenTile = RNGX_GEN_TILE;
+
+constexpr int gen_tile_depth(int wg) { return wg * (kGenTile + 4) * 4 <= 160 * 1024 ? kGenTile : 32; }
 
 // Staged store schedule: 1 = whole tile at once, 2 = software-pipelined.
 #ifndef RNGX_STORE_MODE
@@ -24,11 +27,11 @@ constexpr int kGenTile = RNGX_GEN_TILE;
 constexpr int kStoreMode = RNGX_STORE_MODE;
 
 // Resident schedule for one-chunk launches of whole stream groups: a wave
-// preloads the states of up to kResidentGroups groups before its first store.
-#ifndef RNGX_RESIDENT_GROUPS
-#define RNGX_RESIDENT_GROUPS 8
-#endif
-constexpr int kResidentGroups = RNGX_RESIDENT_GROUPS;
+// preloads the states of all its groups before its first store.  The register
+// queue holds up to this many groups: enough for 2^20 streams on the waves the
+// device holds at once with each shape (4 per CU with 128-deep tiles, 16 with
+// 32-deep ones), within the registers each shape leaves.
+constexpr int resident_groups(int wg, int depth) { return depth >= 128 ? 16 : (wg >= 1024 ? 4 : 8); }
 
 struct GenArgs {
     uint32_t *state;  // [W][ld]

@@ -124,24 +124,24 @@ __device__ __forceinline__ void store_tile(const uint32_t *tile, uint32_t *out, 
             }
         }
     } else {
-        constexpr int RPI = 64 / K;      // rows per store instruction (K <= 64)
-        const int r0 = lane / K, c = lane % K;
+        // word stores: each instruction covers RPI rows x W consecutive words
+        constexpr int W = K < 64 ? K : 64, RPI = 64 / W, CPR = K / W;
+        const int r0 = lane / W, c = lane % W;
         const uint32_t *src = tile + r0 * LD + c;
         uint32_t *dst = out + (s0 + r0) * N + k0 + c;
-        if (rows == 64 && cnt == K) {
-            uint32_t v[K];
+        const bool full = rows == 64 && cnt == K;
+#pragma unroll 4
+        for (int i = 0; i < 64 / RPI; ++i) {
 #pragma unroll
-            for (int i = 0; i < K; ++i) v[i] = src[i * RPI * LD];
-#pragma unroll
-            for (int i = 0; i < K; ++i) {
-                uint32_t *d = dst + (uint64_t)(i * RPI) * N;
-                if (nt) __builtin_nontemporal_store(v[i], d);
-                else *d = v[i];
+            for (int j = 0; j < CPR; ++j) {
+                const uint32_t r = r0 + i * RPI, col = j * W + c;
+                if (full || (r < rows && col < cnt)) {
+                    uint32_t *d = dst + (uint64_t)(i * RPI) * N + j * W;
+                    const uint32_t v = src[i * RPI * LD + j * W];
+                    if (nt) __builtin_nontemporal_store(v, d);
+                    else *d = v;
+                }
             }
-        } else {
-#pragma unroll
-            for (int i = 0; i < K; ++i)
-                if ((uint32_t)(r0 + i * RPI) < rows && (uint32_t)c < cnt) dst[(uint64_t)(i * RPI) * N] = src[i * RPI * LD];
         }
     }
 }
@@ -182,16 +182,16 @@ __device__ __forceinline__ void gen_to_row(G &g, uint32_t *row, int k)
 // Resident form of the pipelined schedule, for launches with one chunk per
 // stream, whole 64-stream groups and N a multiple of K.  The grid holds the
 // waves that fit on the device; wave w takes groups w, w + W, w + 2W, ... (at
-// most kResidentGroups).  It loads all their states first and waits for them
+// most MG).  It loads all their states first and waits for them
 // once, before its first store, then only writes: the vector memory counter
 // retires loads and stores in issue order, so any later wait for a load
 // would also wait for every store still in flight.  The store pipeline runs
 // across group boundaries, and the states move down a register queue.
-template <class G, int DT, int U, int K>
+template <class G, int DT, int U, int K, int MG>
 __device__ __forceinline__ void gen_resident(const GenArgs &a, uint32_t *tile, int lane, uint64_t wave,
                                              uint64_t nwaves)
 {
-    constexpr int LD = K + 4, QPR = K / 4, RPI = 64 / QPR, MG = kResidentGroups;
+    constexpr int LD = K + 4, QPR = K / 4, RPI = 64 / QPR;
     const int r0 = lane / QPR, q = lane % QPR;
     const uint32_t *src = tile + r0 * LD + 4 * q;
     uint32_t *row = tile + lane * LD;
@@ -258,7 +258,8 @@ __global__ __launch_bounds__(WG) void k_generate(GenArgs a)
     const uint64_t wave = (uint64_t)blockIdx.x * NW + wv;
     if constexpr (kMode == 2) {
         if (a.resident) {
-            gen_resident<G, DT, U, K>(a, &lds[wv * 64 * LD], lane, wave, (uint64_t)gridDim.x * NW);
+            gen_resident<G, DT, U, K, resident_groups(WG, K)>(a, &lds[wv * 64 * LD], lane, wave,
+                                                              (uint64_t)gridDim.x * NW);
             return;
         }
     }
@@ -480,13 +481,13 @@ int launch_generate_shape(const GenArgs &a, hipStream_t stream)
     // tile depth: kGenTile unless the workgroup's tiles would not fit in the
     // 160 KiB of LDS, then 32 (chunk lengths are multiples of kGenTile, so
     // of both depths)
-    constexpr int K = (WG * (kGenTile + 4) * 4 <= 160 * 1024) ? kGenTile : 32;
+    constexpr int K = gen_tile_depth(WG);
     GenArgs b = a;
     b.resident = 0;
     if constexpr (kMode == 2) {
         if (a.P == 1 && a.vec4 && a.S % 64 == 0 && a.N % K == 0) {
             // the workgroups resident at once; each wave then takes at most
-            // kResidentGroups groups
+            // resident_groups(WG, K) groups
             static const uint64_t resident = [] {
                 int per_cu = 0, dev = 0, cus = 0;
                 if (hipGetDevice(&dev) != hipSuccess ||
@@ -496,7 +497,7 @@ int launch_generate_shape(const GenArgs &a, hipStream_t stream)
                     return (uint64_t)0;
                 return (uint64_t)per_cu * (uint64_t)cus;
             }();
-            if (resident && blocks <= resident * kResidentGroups) {
+            if (resident && blocks <= resident * resident_groups(WG, K)) {
                 b.resident = 1;
                 if (blocks > resident) blocks = resident;
             }
