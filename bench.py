@@ -478,14 +478,15 @@ def cpu_baseline(seconds):
                       "step, %.1f s of wall time" % (reps, S, N_BULK, len(gens), total_t)}
 
 
-KERNEL_SOURCES = ["rng_device.hpp", "rng_kernels.hpp", "rng_internal.hpp"]
+KERNEL_SOURCES = ["paper_1101_1846_amd/csrc/rng_device.hpp", "paper_1101_1846_amd/csrc/rng_kernels.hpp",
+                  "paper_1101_1846_amd/csrc/rng_internal.hpp", "include/rng_inline.hpp"]
 
 
 def kernel_source_sha():
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1101_1846_amd", "csrc", f), "rb") as fh:
+        with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 

@@ -1,17 +1,16 @@
-// rng_device.hpp -- HIP device functions for the generators of Hissoiny,
-// Despres & Ozell (arXiv:1101.1846): state load/store, one step, seeding,
-// jump-ahead and the FP32 map.  The library's kernels are built from these,
-// and another kernel can include this header to draw numbers inline (the
-// "on the fly" use the paper discusses in Sec. III.A.2 and III.B).
-//
-// Each generator is a small struct whose state lives in VGPRs:
-//   load(state, S, s) / store(state, S, s)  structure-of-arrays [W][S]
-//   next()                                   step, then emit (eq. (1))
-//   jump(k, tab)                             advance by k steps
-//   seed(d, tab)                             state from SplitMix64 draws d[]
+// rng_device.hpp -- the library's device view of the generators of
+// Hissoiny, Despres & Ozell (arXiv:1101.1846).  Each Gen* struct is the
+// public step type of include/rng_inline.hpp (state in VGPRs, load/store of
+// the structure-of-arrays [W][S] layout, next() = step then emit, eq. (1))
+// plus what the library's kernels also need:
+//   load(state, S, s, tab)   as load(state, S, s)
+//   jump(k, tab)             advance by k steps (device tables below)
+//   seed(d, tab)             state from SplitMix64 draws d[]
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "rng_inline.hpp"
 
 namespace rngx {
 
@@ -27,10 +26,9 @@ struct DevTables {
     uint64_t mwc32_m;              // a * 2^32 - 1
 };
 
-__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
-{
-    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
-}
+using rng_inline::detail::xor3;
+using rng_inline::detail::mwc16_step;
+using rng_inline::to_unit_f32;
 
 // SplitMix64 output number n of a generator started at `seed`
 // (Steele, Lea & Flood 2014): mix(seed + (n+1) * gamma).
@@ -40,12 +38,6 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t n)
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
-}
-
-// The exact FP32 uniform: top 24 bits times 2^-24.
-__device__ __forceinline__ float to_unit_f32(uint32_t u)
-{
-    return (float)(u >> 8) * 0x1p-24f;
 }
 
 // ---------------------------------------------------------------- MWC algebra
@@ -157,27 +149,13 @@ __device__ __forceinline__ void stage_t4(uint4 *lds, const uint4 *T)
 // ---------------------------------------------------------------- generators
 enum { G_MWC32 = 1, G_XS256 = 2, G_XS32 = 3, G_KISS = 4, G_MWC1616 = 5 };
 
-// Eq. (2)-(3), b = 2^32: t = a*x + c (one 32x32+32 -> 64 multiply-add).
-struct GenMWC32 {
+// Eq. (2)-(3), b = 2^32 (rng_inline::MWC32).
+struct GenMWC32 : rng_inline::MWC32 {
     static constexpr int kId = G_MWC32, W = 2, D = 1;
-    uint32_t x, c, a;
-    __device__ void load(const uint32_t *st, uint64_t S, uint64_t s, const DevTables &tab)
+    using rng_inline::MWC32::load;
+    __device__ __forceinline__ void load(const uint32_t *st, uint64_t S, uint64_t s, const DevTables &)
     {
-        x = st[s];
-        c = st[S + s];
-        a = tab.mwc32_a;
-    }
-    __device__ void store(uint32_t *st, uint64_t S, uint64_t s) const
-    {
-        st[s] = x;
-        st[S + s] = c;
-    }
-    __device__ __forceinline__ uint32_t next()
-    {
-        uint64_t t = (uint64_t)a * x + c;
-        x = (uint32_t)t;
-        c = (uint32_t)(t >> 32);
-        return x;
+        load(st, S, s);
     }
     __device__ void jump(uint64_t k, const DevTables &tab)
     {
@@ -189,8 +167,7 @@ struct GenMWC32 {
     }
     __device__ void seed(const uint64_t *d, const DevTables &tab)
     {
-        a = tab.mwc32_a;
-        uint64_t z = (uint64_t)((uint32_t)(d[0] >> 32) % a) << 32 | (uint32_t)d[0];
+        uint64_t z = (uint64_t)((uint32_t)(d[0] >> 32) % tab.mwc32_a) << 32 | (uint32_t)d[0];
         z = z == 0 ? 1 : z;
         z = z == tab.mwc32_m ? tab.mwc32_m - 1 : z;
         x = (uint32_t)z;
@@ -198,34 +175,15 @@ struct GenMWC32 {
     }
 };
 
-// Eq. (5): window v[0..7] = (v_{n-8} .. v_{n-1}).  14 VALU operations per
-// number on gfx950 (7 shifts, 2 two-input and 5 three-input xors) against
-// the paper's 18 two-input operations.
-struct GenXS256 {
+// Eq. (5), r = 8 (rng_inline::XS256): window v[0..7] = (v_{n-8} .. v_{n-1}).
+// 14 VALU operations per number on gfx950 (7 shifts, 2 two-input and 5
+// three-input xors) against the paper's 18 two-input operations.
+struct GenXS256 : rng_inline::XS256 {
     static constexpr int kId = G_XS256, W = 8, D = 4;
-    uint32_t v[8];
-    __device__ void load(const uint32_t *st, uint64_t S, uint64_t s, const DevTables &)
+    using rng_inline::XS256::load;
+    __device__ __forceinline__ void load(const uint32_t *st, uint64_t S, uint64_t s, const DevTables &)
     {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] = st[i * S + s];
-    }
-    __device__ void store(uint32_t *st, uint64_t S, uint64_t s) const
-    {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) st[i * S + s] = v[i];
-    }
-    __device__ __forceinline__ uint32_t next()
-    {
-        uint32_t u1 = v[7] ^ (v[7] << 13);   // (I+L^13) v_{n-1}
-        uint32_t u8 = v[0] ^ (v[0] >> 7);    // (I+R^7) v_{n-8}
-        uint32_t p = xor3(u1, u1 << 9, v[4]);              // (I+L^9)(.) + v_{n-4}
-        uint32_t q = xor3(v[4] << 7, v[3], v[3] >> 3);      // L^7 v_{n-4} + (I+R^3) v_{n-5}
-        uint32_t r = xor3(v[1], v[1] >> 10, u8);            // (I+R^10) v_{n-7} + u8
-        uint32_t vn = xor3(p, q, r) ^ (u8 << 24);           // + L^24 u8
-#pragma unroll
-        for (int i = 0; i < 7; ++i) v[i] = v[i + 1];
-        v[7] = vn;
-        return vn;
+        load(st, S, s);
     }
     __device__ void jump(uint64_t k, const DevTables &tab)
     {
@@ -247,18 +205,13 @@ struct GenXS256 {
     }
 };
 
-// Eq. (6): y ^= y<<13; y ^= y>>17; y ^= y<<5.
-struct GenXS32 {
+// Eq. (6) (rng_inline::XS32).
+struct GenXS32 : rng_inline::XS32 {
     static constexpr int kId = G_XS32, W = 1, D = 1;
-    uint32_t y;
-    __device__ void load(const uint32_t *st, uint64_t, uint64_t s, const DevTables &) { y = st[s]; }
-    __device__ void store(uint32_t *st, uint64_t, uint64_t s) const { st[s] = y; }
-    __device__ __forceinline__ uint32_t next()
+    using rng_inline::XS32::load;
+    __device__ __forceinline__ void load(const uint32_t *st, uint64_t S, uint64_t s, const DevTables &)
     {
-        y ^= y << 13;
-        y ^= y >> 17;
-        y ^= y << 5;
-        return y;
+        load(st, S, s);
     }
     __device__ void jump(uint64_t k, const DevTables &tab)
     {
@@ -272,38 +225,14 @@ struct GenXS32 {
     }
 };
 
-// One base-2^16 MWC word z = c*2^16 + x: z <- a*(z & 0xFFFF) + (z >> 16)
-// (eq. (2)-(3) with the mask and shift of Sec. II.A.1).  Both factors are
-// below 2^16, so the 24-bit multiply(-add) is exact.
-__device__ __forceinline__ uint32_t mwc16_step(uint32_t z, uint32_t a)
-{
-    return __umul24(a, z & 0xFFFFu) + (z >> 16);
-}
 
-// Sec. III.A.1: the paper's MWC, two base-2^16 words with distinct
-// multipliers, output (z << 16) + w.
-struct GenMWC1616 {
+// Sec. III.A.1: two base-2^16 MWC words (rng_inline::MWC1616).
+struct GenMWC1616 : rng_inline::MWC1616 {
     static constexpr int kId = G_MWC1616, W = 4, D = 2;
-    uint32_t z, w, a1, a2;
-    __device__ void load(const uint32_t *st, uint64_t S, uint64_t s, const DevTables &)
+    using rng_inline::MWC1616::load;
+    __device__ __forceinline__ void load(const uint32_t *st, uint64_t S, uint64_t s, const DevTables &)
     {
-        z = st[s];
-        w = st[S + s];
-        a1 = st[2 * S + s];
-        a2 = st[3 * S + s];
-    }
-    __device__ void store(uint32_t *st, uint64_t S, uint64_t s) const
-    {
-        st[s] = z;
-        st[S + s] = w;
-        st[2 * S + s] = a1;
-        st[3 * S + s] = a2;
-    }
-    __device__ __forceinline__ uint32_t next()
-    {
-        z = mwc16_step(z, a1);
-        w = mwc16_step(w, a2);
-        return (z << 16) + w;
+        load(st, S, s);
     }
     __device__ void jump(uint64_t k, const DevTables &tab)
     {
@@ -324,36 +253,12 @@ struct GenMWC1616 {
 };
 
 // Sec. II.A.3 / III.A.3: KISS = (MWC1616 xor LCG) + XS32, LCG of eq. (7).
-struct GenKISS {
+struct GenKISS : rng_inline::KISS {
     static constexpr int kId = G_KISS, W = 6, D = 3;
-    uint32_t z, w, jsr, jcong, a1, a2;
-    __device__ void load(const uint32_t *st, uint64_t S, uint64_t s, const DevTables &)
+    using rng_inline::KISS::load;
+    __device__ __forceinline__ void load(const uint32_t *st, uint64_t S, uint64_t s, const DevTables &)
     {
-        z = st[s];
-        w = st[S + s];
-        jsr = st[2 * S + s];
-        jcong = st[3 * S + s];
-        a1 = st[4 * S + s];
-        a2 = st[5 * S + s];
-    }
-    __device__ void store(uint32_t *st, uint64_t S, uint64_t s) const
-    {
-        st[s] = z;
-        st[S + s] = w;
-        st[2 * S + s] = jsr;
-        st[3 * S + s] = jcong;
-        st[4 * S + s] = a1;
-        st[5 * S + s] = a2;
-    }
-    __device__ __forceinline__ uint32_t next()
-    {
-        z = mwc16_step(z, a1);
-        w = mwc16_step(w, a2);
-        jcong = 69069u * jcong + 1234567u;
-        jsr ^= jsr << 13;
-        jsr ^= jsr >> 17;
-        jsr ^= jsr << 5;
-        return (((z << 16) + w) ^ jcong) + jsr;
+        load(st, S, s);
     }
     __device__ void jump(uint64_t k, const DevTables &tab)
     {

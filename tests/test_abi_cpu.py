@@ -120,3 +120,15 @@ def test_product_never_imports_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "rng_oracle" not in text and "liboracle" not in text, f
+
+
+def test_inline_consumer_built_on_public_headers():
+    """The on-the-fly consumer is built from include/ alone and exports its entry."""
+    import ctypes
+    here = os.path.dirname(os.path.abspath(__file__))
+    lib = os.path.join(here, "inline", "libonthefly.so")
+    assert os.path.exists(lib), "tests/inline/libonthefly.so is not built (run __graft_entry__.build())"
+    assert hasattr(ctypes.CDLL(lib), "onthefly_draw")
+    src = open(os.path.join(here, "inline", "onthefly.hip")).read()
+    includes = [l.split()[1] for l in src.splitlines() if l.startswith("#include")]
+    assert set(includes) == {"<hip/hip_runtime.h>", "<stdint.h>", '"rng.h"', '"rng_inline.hpp"'}
