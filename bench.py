@@ -44,7 +44,7 @@ def parse():
     p.add_argument("--no-extra", action="store_true", help="skip the side workloads")
     p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--no-tune", action="store_true", help="keep the library's default launch shapes")
-    p.add_argument("--only", choices=["batched", "served", "split", "fused", "small"],
+    p.add_argument("--only", choices=["batched", "served", "split", "fused", "small", "placement"],
                    help="run one side workload alone and print its JSON record")
     p.add_argument("--profile", metavar="GEN_DTYPE",
                    help="counter-collection mode: a 1 GiB device copy (calibration) then 3 launches of "
@@ -251,7 +251,7 @@ def _time(torch, fn, reps):
 
 def side_workloads(torch, R, dev, stream, only=None):
     """Every workload besides the timed step, or only the one named."""
-    parts = {"small": small_workloads, "split": split_workload}
+    parts = {"small": small_workloads, "split": split_workload, "placement": placement_workload}
     res = {}
     if only in parts:
         res.update(parts[only](torch, R, dev))
@@ -270,6 +270,7 @@ def side_workloads(torch, R, dev, stream, only=None):
     res["batched_10k_requests"] = batched_workload(torch, R, dev)
     res["served"] = served_workload(R, res["batched_10k_requests"]["single_large_call_GSamples_s"])
     res.update(fused_workload(torch, R, dev))
+    res.update(placement_workload(torch, R, dev))
     torch.cuda.empty_cache()
     return res
 
@@ -318,6 +319,39 @@ def split_workload(torch, R, dev):
                                        "GB_s": round(4 * total / (ms * 1e-3) / 1e9, 1)}
     del o
     return res
+
+
+# The paper's XorShift placement table on its GTX280 (GSamples/s with and without write-back for the
+# implicit, explicit and register forms), quoted for context only: other hardware, its own sizes.
+PAPER_TABLE2_RATE = {"lds_indexed": (4.4, 4.8), "lds_unrolled": (8.1, 13.8), "vgpr": (12.5, 14.5)}
+XS256_USEFUL_OPS = 18  # useful operations per XorShift number (11 XORs, 7 shifts)
+
+
+def placement_workload(torch, R, dev):
+    """The XorShift state placements of the paper's Table II at 2^20 streams x 256:
+    with write-back (every number stored, sample-major) and without (per-stream XOR)."""
+    S, N = S_BULK, N_BULK
+    st = torch.empty((8, S), dtype=torch.int32, device=dev)
+    R.rng_seed(R.RNG_XS256, 1, 0, S, st)
+    out = torch.empty(S * N, dtype=torch.int32, device=dev)
+    fold = torch.empty(S, dtype=torch.int32, device=dev)
+    res = {}
+    for name, pl in R.PLACEMENTS.items():
+        row = {}
+        for dname, d in R.DTYPES.items():
+            ms_wb = _time(torch, lambda: R.rng_xs256_placement(pl, st, S, N, d, d_out=out), 10)
+            ms_nw = _time(torch, lambda: R.rng_xs256_placement(pl, st, S, N, d, d_fold=fold), 10)
+            rate_wb, rate_nw = S * N / (ms_wb * 1e-3), S * N / (ms_nw * 1e-3)
+            row[dname] = {"with_writeback": {"ms": round(ms_wb, 4), "GSamples_s": round(rate_wb / 1e9, 1),
+                                             "GB_s": round((4 * S * N + 64 * S) / (ms_wb * 1e-3) / 1e9, 1),
+                                             "useful_Gops": round(rate_wb * XS256_USEFUL_OPS / 1e9, 1)},
+                          "without_writeback": {"ms": round(ms_nw, 4), "GSamples_s": round(rate_nw / 1e9, 1),
+                                                "useful_Gops": round(rate_nw * XS256_USEFUL_OPS / 1e9, 1)}}
+        row["paper_gtx280_GSamples_s"] = dict(zip(("with_writeback", "without_writeback"), PAPER_TABLE2_RATE[name]))
+        res[name] = row
+    del out
+    torch.cuda.empty_cache()
+    return {"xs256_placement_2^20x256": res}
 
 
 def fused_workload(torch, R, dev):

@@ -152,6 +152,29 @@ int rng_generate_split(int g, const uint32_t *d_state_one, uint64_t total, uint6
 int rng_fused_pi(int g, uint32_t *d_state, uint64_t n_streams, uint64_t n,
                  uint64_t *d_count, void *stream);
 
+/* The paper's XorShift placement comparison (Sec. III.A.2, Table II): the
+ * r = 8 XorShift (eq. (5)) with each thread's eight state words
+ *   RNG_XS_LDS_INDEXED   in LDS, read and written through a runtime
+ *                        circular index (the reference C code's form);
+ *   RNG_XS_LDS_UNROLLED  in LDS, circular buffer made explicit by an 8-fold
+ *                        unroll (constant offsets);
+ *   RNG_XS_VGPR          in registers (the library's own form).
+ * The state words sit blockDim-strided in LDS (word i of thread t at
+ * i * 256 + t), the paper's bank-conflict-free layout, and every LDS access is
+ * a real load or store.  All three give the same numbers as rng_generate.
+ * One thread per stream, 256-thread workgroups; d_state is [8][n_streams]
+ * (as rng_seed writes it) and is advanced by n.
+ *   d_out  : with write-back, [n][n_streams] sample-major (number k of stream
+ *            s at d_out[k * n_streams + s]), uint32 or FP32 per t;
+ *   d_fold : without write-back, [n_streams] XOR of each stream's n outputs
+ *            (FP32 bit patterns when t = RNG_F32); nothing else is stored.
+ * Exactly one of d_out and d_fold is non-NULL (else RNG_EINVAL); n_streams
+ * at most 2^31.  Meant for measuring what the placement costs, not as a
+ * faster path. */
+typedef enum { RNG_XS_LDS_INDEXED = 0, RNG_XS_LDS_UNROLLED = 1, RNG_XS_VGPR = 2 } rng_xs_placement_t;
+int rng_xs256_placement(int placement, uint32_t *d_state, uint64_t n_streams, uint64_t n, int t,
+                        void *d_out, uint32_t *d_fold, void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* Batched generation: thousands of independent requests of uneven length  */
 /* in one persistent launch captured in a HIP graph.  Each request is the   */

@@ -96,15 +96,21 @@ struct XS256 {
 #pragma unroll
         for (int i = 0; i < 8; ++i) st[i * S + s] = v[i];
     }
-    __device__ __forceinline__ uint32_t next()
+    // v_n from the five taps of eq. (5): v_{n-1}, v_{n-4}, v_{n-5}, v_{n-7}, v_{n-8}.
+    static __device__ __forceinline__ uint32_t step(uint32_t m1, uint32_t m4, uint32_t m5, uint32_t m7,
+                                                    uint32_t m8)
     {
         using detail::xor3;
-        const uint32_t u1 = v[7] ^ (v[7] << 13);              // (I+L^13) v_{n-1}
-        const uint32_t u8 = v[0] ^ (v[0] >> 7);               // (I+R^7) v_{n-8}
-        const uint32_t p = xor3(u1, u1 << 9, v[4]);           // (I+L^9)(.) + v_{n-4}
-        const uint32_t q = xor3(v[4] << 7, v[3], v[3] >> 3);  // L^7 v_{n-4} + (I+R^3) v_{n-5}
-        const uint32_t r = xor3(v[1], v[1] >> 10, u8);        // (I+R^10) v_{n-7} + u8
-        const uint32_t vn = xor3(p, q, r) ^ (u8 << 24);       // + L^24 u8
+        const uint32_t u1 = m1 ^ (m1 << 13);             // (I+L^13) v_{n-1}
+        const uint32_t u8 = m8 ^ (m8 >> 7);              // (I+R^7) v_{n-8}
+        const uint32_t p = xor3(u1, u1 << 9, m4);        // (I+L^9)(.) + v_{n-4}
+        const uint32_t q = xor3(m4 << 7, m5, m5 >> 3);   // L^7 v_{n-4} + (I+R^3) v_{n-5}
+        const uint32_t r = xor3(m7, m7 >> 10, u8);       // (I+R^10) v_{n-7} + u8
+        return xor3(p, q, r) ^ (u8 << 24);               // + L^24 u8
+    }
+    __device__ __forceinline__ uint32_t next()
+    {
+        const uint32_t vn = step(v[7], v[4], v[3], v[1], v[0]);
 #pragma unroll
         for (int i = 0; i < 7; ++i) v[i] = v[i + 1];
         v[7] = vn;

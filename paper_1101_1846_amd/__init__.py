@@ -20,6 +20,8 @@ RNG_U32, RNG_F32 = 0, 1
 GENERATORS = {"MWC32": RNG_MWC32, "XS256": RNG_XS256, "XS32": RNG_XS32, "KISS": RNG_KISS,
               "MWC1616": RNG_MWC1616}
 DTYPES = {"u32": RNG_U32, "f32": RNG_F32}
+RNG_XS_LDS_INDEXED, RNG_XS_LDS_UNROLLED, RNG_XS_VGPR = 0, 1, 2
+PLACEMENTS = {"lds_indexed": RNG_XS_LDS_INDEXED, "lds_unrolled": RNG_XS_LDS_UNROLLED, "vgpr": RNG_XS_VGPR}
 RNG_OK, RNG_EINVAL, RNG_ERANGE, RNG_ENOMEM, RNG_EHIP, RNG_ENODEV, RNG_EAGAIN = 0, -1, -2, -3, -4, -5, -6
 
 if not os.path.exists(LIB_PATH):
@@ -53,6 +55,7 @@ _SIGS = {
     "rng_generate_split": (_int, [_int, _vp, _u64, _u64, _int, _vp, _vp, _vp, _u64, _vp]),
     "rng_fused_pi": (_int, [_int, _vp, _u64, _u64, _vp, _vp]),
     "rng_calibrate_valu": (_int, [_int, ctypes.POINTER(ctypes.c_double), _vp]),
+    "rng_xs256_placement": (_int, [_int, _vp, _u64, _u64, _int, _vp, _vp, _vp]),
 }
 
 
@@ -230,6 +233,11 @@ def rng_generate_split(g, d_state_one, total, n_threads, t, d_out, d_final_state
 def rng_fused_pi(g, d_state, n_streams, n, d_count, stream=None):
     return _check(_lib.rng_fused_pi(g, _ptr(d_state), n_streams, n, _ptr(d_count), _stream(stream)),
                   "rng_fused_pi")
+
+
+def rng_xs256_placement(placement, d_state, n_streams, n, t, d_out=None, d_fold=None, stream=None):
+    return _check(_lib.rng_xs256_placement(placement, _ptr(d_state), n_streams, n, t, _ptr(d_out), _ptr(d_fold),
+                                           _stream(stream)), "rng_xs256_placement")
 
 
 def rng_calibrate_valu(op, stream=None):

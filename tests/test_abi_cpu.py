@@ -132,3 +132,15 @@ def test_inline_consumer_built_on_public_headers():
     src = open(os.path.join(here, "inline", "onthefly.hip")).read()
     includes = [l.split()[1] for l in src.splitlines() if l.startswith("#include")]
     assert set(includes) == {"<hip/hip_runtime.h>", "<stdint.h>", '"rng.h"', '"rng_inline.hpp"'}
+
+
+def test_placement_argument_errors():
+    """Argument checks of rng_xs256_placement, taken before any device call."""
+    import paper_1101_1846_amd as R
+    L = R.raw()
+    assert L.rng_xs256_placement(3, None, 1, 1, 0, 16, None, None) == R.RNG_EINVAL
+    assert L.rng_xs256_placement(-1, None, 1, 1, 0, 16, None, None) == R.RNG_EINVAL
+    assert L.rng_xs256_placement(0, None, 1, 1, 2, 16, None, None) == R.RNG_EINVAL
+    assert L.rng_xs256_placement(0, None, 1, 1, 0, None, None, None) == R.RNG_EINVAL
+    assert L.rng_xs256_placement(0, None, 1, 1, 0, 16, 16, None) == R.RNG_EINVAL
+    assert L.rng_xs256_placement(2, None, 0, 5, 1, None, 16, None) == R.RNG_OK
