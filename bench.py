@@ -301,7 +301,7 @@ def small_workloads(torch, R, dev):
 
 
 def split_workload(torch, R, dev):
-    """Jump-ahead split of one 2^30-sample sequence over 2^20 threads."""
+    """One 2^30-sample sequence over 2^20 threads: jump-ahead splitting, and leapfrogging."""
     res = {}
     total, T = 1 << 30, 1 << 20
     o = torch.empty(total, dtype=torch.int32, device=dev)
@@ -317,6 +317,21 @@ def split_workload(torch, R, dev):
         res["split_2^30_%s" % name] = {"ms": round(ms, 3),
                                        "GSamples_s": round(total / (ms * 1e-3) / 1e9, 1),
                                        "GB_s": round(4 * total / (ms * 1e-3) / 1e9, 1)}
+        del ws
+    # the same sequence by leapfrogging: thread j emits numbers j, j + T, ...
+    for name in ("MWC32", "XS32", "KISS", "MWC1616", "XS256"):
+        g = R.GENERATORS[name]
+        W = R.rng_state_words(g)
+        s1 = torch.empty(W, dtype=torch.int32, device=dev)
+        R.rng_seed(g, 2, 0, 1, s1)
+        fin = torch.empty(W, dtype=torch.int32, device=dev)
+        wsb = R.rng_leapfrog_workspace_bytes(g, T)
+        ws = torch.empty(wsb // 4, dtype=torch.int32, device=dev)
+        ms = _time(torch, lambda: R.rng_generate_leapfrog(g, s1, total, T, R.RNG_U32, o, fin, ws, wsb), 3)
+        res["leapfrog_2^30_%s" % name] = {"ms": round(ms, 3),
+                                          "GSamples_s": round(total / (ms * 1e-3) / 1e9, 1),
+                                          "GB_s": round(4 * total / (ms * 1e-3) / 1e9, 1)}
+        del ws
     del o
     return res
 

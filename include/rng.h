@@ -142,6 +142,25 @@ int rng_generate_split(int g, const uint32_t *d_state_one, uint64_t total, uint6
                        int t, void *d_out, uint32_t *d_final_state, void *d_workspace,
                        uint64_t workspace_bytes, void *stream);
 
+/* Leapfrogging (Sec. II.A.4): the same sequence and output as
+ * rng_generate_split, computed the other way round.  With T = min(n_threads,
+ * total) threads, thread j emits numbers j, j + T, j + 2T, ... of the serial
+ * sequence, so d_out[i] is number i and every wave stores 64 consecutive
+ * numbers.  Thread j starts at the state after j steps (a doubling tree of
+ * jumps), steps once, and then advances T steps per number with the
+ * generator's T-step map: one modular multiply per MWC word, a 32x32 GF(2)
+ * product for xorshift32, a 256x256 one for XS256 (through a 4-bit table of
+ * M^T in LDS), an affine map for the LCG.  d_out[0 .. total) equals the
+ * serial sequence; the advanced state goes to d_final_state ([words], device;
+ * may alias d_state_one).  d_workspace of at least
+ * rng_leapfrog_workspace_bytes(g, T) bytes, 256-byte aligned, caller owned,
+ * holds the thread states and the T-step constants.  Errors as
+ * rng_generate_split. */
+int rng_leapfrog_workspace_bytes(int g, uint64_t n_threads, uint64_t *bytes);
+int rng_generate_leapfrog(int g, const uint32_t *d_state_one, uint64_t total, uint64_t n_threads,
+                          int t, void *d_out, uint32_t *d_final_state, void *d_workspace,
+                          uint64_t workspace_bytes, void *stream);
+
 /* Fused consumer (the paper's "without write-back" mode, Sec. III.B, made to
  * consume every sample): each stream draws n samples; consecutive pairs
  * (u_{2k}, u_{2k+1}) give i = u_{2k} >> 8, j = u_{2k+1} >> 8 and count when

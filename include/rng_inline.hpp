@@ -20,8 +20,10 @@
 //   KISS     6       z, w, jsr, jcong, a1, a2         Sec. III.A.3: (MWC1616 ^ LCG) + XS32, eq. (7)
 //
 // next() steps the recurrence once and returns the new 32-bit output (the
-// step-then-emit convention of eq. (1)).  to_unit_f32(u) maps an output to
-// the exact single-precision uniform (u >> 8) * 2^-24 in [0, 1).
+// step-then-emit convention of eq. (1)); last() returns the output of the
+// most recent step again (every output is a function of the state the step
+// left).  to_unit_f32(u) maps an output to the exact single-precision
+// uniform (u >> 8) * 2^-24 in [0, 1).
 //
 // Header only, written for gfx950; it allocates nothing, launches nothing and
 // holds no global state.  load() and store() must be called with the same
@@ -77,6 +79,7 @@ struct MWC32 {
         c = (uint32_t)(t >> 32);
         return x;
     }
+    __device__ __forceinline__ uint32_t last() const { return x; }
 };
 
 // Eq. (5), r = 8: v_n = (I+L^9)(I+L^13) v_{n-1} + (I+L^7) v_{n-4}
@@ -116,6 +119,7 @@ struct XS256 {
         v[7] = vn;
         return vn;
     }
+    __device__ __forceinline__ uint32_t last() const { return v[7]; }
 };
 
 // Eq. (6): y ^= y << 13; y ^= y >> 17; y ^= y << 5.
@@ -131,6 +135,7 @@ struct XS32 {
         y ^= y << 5;
         return y;
     }
+    __device__ __forceinline__ uint32_t last() const { return y; }
 };
 
 // Sec. III.A.1: two base-2^16 MWC words with their own multipliers (carried in
@@ -158,6 +163,7 @@ struct MWC1616 {
         w = detail::mwc16_step(w, a2);
         return (z << 16) + w;
     }
+    __device__ __forceinline__ uint32_t last() const { return (z << 16) + w; }
 };
 
 // Sec. II.A.3 / III.A.3: KISS = ((MWC1616 output) ^ LCG) + XS32, with the
@@ -191,8 +197,9 @@ struct KISS {
         jsr ^= jsr << 13;
         jsr ^= jsr >> 17;
         jsr ^= jsr << 5;
-        return (((z << 16) + w) ^ jcong) + jsr;
+        return last();
     }
+    __device__ __forceinline__ uint32_t last() const { return (((z << 16) + w) ^ jcong) + jsr; }
 };
 
 }  // namespace rng_inline

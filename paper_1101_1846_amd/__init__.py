@@ -56,6 +56,8 @@ _SIGS = {
     "rng_fused_pi": (_int, [_int, _vp, _u64, _u64, _vp, _vp]),
     "rng_calibrate_valu": (_int, [_int, ctypes.POINTER(ctypes.c_double), _vp]),
     "rng_xs256_placement": (_int, [_int, _vp, _u64, _u64, _int, _vp, _vp, _vp]),
+    "rng_leapfrog_workspace_bytes": (_int, [_int, _u64, _pu64]),
+    "rng_generate_leapfrog": (_int, [_int, _vp, _u64, _u64, _int, _vp, _vp, _vp, _u64, _vp]),
 }
 
 
@@ -228,6 +230,19 @@ def rng_generate_split(g, d_state_one, total, n_threads, t, d_out, d_final_state
     return _check(_lib.rng_generate_split(g, _ptr(d_state_one), total, n_threads, t, _ptr(d_out),
                                           _ptr(d_final_state), _ptr(d_workspace), workspace_bytes,
                                           _stream(stream)), "rng_generate_split")
+
+
+def rng_leapfrog_workspace_bytes(g, n_threads):
+    b = ctypes.c_uint64()
+    _check(_lib.rng_leapfrog_workspace_bytes(g, n_threads, ctypes.byref(b)), "rng_leapfrog_workspace_bytes")
+    return b.value
+
+
+def rng_generate_leapfrog(g, d_state_one, total, n_threads, t, d_out, d_final_state, d_workspace,
+                          workspace_bytes, stream=None):
+    return _check(_lib.rng_generate_leapfrog(g, _ptr(d_state_one), total, n_threads, t, _ptr(d_out),
+                                             _ptr(d_final_state), _ptr(d_workspace), workspace_bytes,
+                                             _stream(stream)), "rng_generate_leapfrog")
 
 
 def rng_fused_pi(g, d_state, n_streams, n, d_count, stream=None):

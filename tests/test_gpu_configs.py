@@ -92,6 +92,33 @@ def test_split_2p30_over_2p20_threads(rng, torch, oracle, name):
     assert np.array_equal(_u32(fin), one)
 
 
+@pytest.mark.parametrize("name", ["MWC32", "XS256", "KISS"])
+def test_leapfrog_2p30_over_2p20_threads(rng, torch, oracle, name):
+    """Leapfrogging one 2^30-sample sequence over 2^20 threads: the same positions,
+    head, tail and final state as the split test, against one serial pass."""
+    g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
+    total, T = 1 << 30, 1 << 20
+    W = rng.rng_state_words(g)
+    s1 = torch.empty(W, dtype=torch.int32, device="cuda")
+    rng.rng_seed(g, 2, 0, 1, s1)
+    fin = torch.empty(W, dtype=torch.int32, device="cuda")
+    wsb = rng.rng_leapfrog_workspace_bytes(g, T)
+    ws = torch.empty(wsb // 4, dtype=torch.int32, device="cuda")
+    out = torch.empty(total, dtype=torch.int32, device="cuda")
+    rng.rng_generate_leapfrog(g, s1, total, T, rng.RNG_U32, out, fin, ws, wsb)
+    pos = np.sort(np.random.default_rng(3).integers(0, total, 10 ** 6, dtype=np.int64))
+    idx = torch.from_numpy(pos).to("cuda")
+    got_pos = _u32(out[idx])
+    head = _u32(out[: 1 << 20])
+    tail = _u32(out[total - (1 << 20):])
+    one = oracle.seed(o, 2, 1)[:, 0].copy()
+    ref_pos, ref_head, ref_tail = oracle.serial_sample(o, one, total, pos.astype(np.uint64), 1 << 20, 1 << 20)
+    assert np.array_equal(got_pos, ref_pos)
+    assert np.array_equal(head, ref_head)
+    assert np.array_equal(tail, ref_tail)
+    assert np.array_equal(_u32(fin), one)
+
+
 def test_fused_pi_2p34_kiss(rng, torch, oracle):
     g = rng.RNG_KISS
     S, N = 1 << 20, 1 << 14

@@ -158,6 +158,43 @@ def test_split_parity(rng, torch, oracle, name, total, threads):
     assert np.array_equal(_host(fin), ref_st[:, 0])
 
 
+@pytest.mark.parametrize("name", GENS)
+@pytest.mark.parametrize("dt", ["u32", "f32"])
+@pytest.mark.parametrize("total,threads", [(1, 1), (1000, 1), (1000, 7), (4096 * 7 + 3, 64), (100000, 1000),
+                                          (65536, 65536), (5, 8), (77777, 4096)])
+def test_leapfrog_parity(rng, torch, oracle, name, dt, total, threads):
+    """Leapfrogging (Sec. II.A.4): thread j's numbers j, j + T, ... interleave into
+    the serial sequence of the one logical stream; the final state matches."""
+    g, o, t = rng.GENERATORS[name], oracle.GENERATORS[name], rng.DTYPES[dt]
+    st1 = _dev_state(torch, rng, g, 2, 1)
+    ws_bytes = rng.rng_leapfrog_workspace_bytes(g, min(threads, total))
+    ws = torch.empty(ws_bytes // 4 + 64, dtype=torch.int32, device="cuda")
+    out = torch.empty(total, dtype=torch.int32, device="cuda")
+    fin = torch.empty(rng.rng_state_words(g), dtype=torch.int32, device="cuda")
+    rng.rng_generate_leapfrog(g, st1, total, threads, t, out, fin, ws, ws_bytes)
+    ref_st = oracle.seed(o, 2, 1)
+    ref = oracle.generate(o, ref_st, total, t)[0].view(np.uint32)
+    assert np.array_equal(_host(out), ref)
+    assert np.array_equal(_host(fin), ref_st[:, 0])
+    assert np.array_equal(_host(st1).ravel(), oracle.seed(o, 2, 1)[:, 0])  # input state untouched
+
+
+def test_leapfrog_arguments(rng, torch):
+    g = rng.RNG_MWC32
+    st1 = _dev_state(torch, rng, g, 2, 1)
+    fin = torch.empty(2, dtype=torch.int32, device="cuda")
+    out = torch.empty(100, dtype=torch.int32, device="cuda")
+    small = torch.empty(8, dtype=torch.int32, device="cuda")
+    with pytest.raises(rng.RngError) as e:
+        rng.rng_generate_leapfrog(g, st1, 100, 10, rng.RNG_U32, out, fin, small, 32)
+    assert e.value.code == rng.RNG_ENOMEM
+    with pytest.raises(rng.RngError) as e:
+        rng.rng_generate_leapfrog(g, st1, 100, 0, rng.RNG_U32, out, fin, small, 32)
+    assert e.value.code == rng.RNG_EINVAL
+    rng.rng_generate_leapfrog(g, st1, 0, 10, rng.RNG_U32, None, fin, None, 0)  # nothing: final = initial
+    assert np.array_equal(_host(fin), _host(st1).ravel())
+
+
 @pytest.mark.parametrize("name", ["KISS", "XS256", "MWC32"])
 @pytest.mark.parametrize("S,N", [(1, 2), (1000, 64), (333, 65), (64, 1000), (2, 40000)])
 def test_fused_pi_parity(rng, torch, oracle, name, S, N):
