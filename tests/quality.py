@@ -54,11 +54,15 @@ def serial_correlation(u):
     return _two_sided_normal(r * np.sqrt(len(u)))
 
 
-def birthday_spacings(u, m=1024, bits=24):
+def birthday_spacings(u, m=512, bits=25):
     """Marsaglia's birthday spacings: m birthdays (top `bits` bits) in a year of
-    n = 2^bits days; the number of repeated values among the sorted spacings
-    is asymptotically Poisson with mean m^3 / (4 n).  Summed over all disjoint
-    blocks of m words, compared with the Poisson of the summed mean."""
+    n = 2^bits days; the number of repeated values among the m - 1 sorted
+    spacings is asymptotically Poisson with mean m^3 / (4 n).  Summed over all
+    disjoint blocks of m words, compared with the Poisson of the summed mean.
+    The limit is accurate only for a small mean: the default (m = 512,
+    n = 2^25, mean 1, error of order m^4 / n^2 = 2^-14) keeps the summed
+    count unbiased; with m = 1024, n = 2^24 (mean 16) a uniform source
+    averages about 15.7, and a sum over thousands of blocks rejects it."""
     k = len(u) // m
     if k == 0:
         return 1.0
