@@ -42,7 +42,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-extra", action="store_true", help="skip the side workloads")
-    p.add_argument("--cpu-seconds", type=float, default=10.0)
+    p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-tune", action="store_true", help="keep the library's default launch shapes")
     p.add_argument("--only", choices=["batched", "served", "split", "fused", "small", "placement"],
                    help="run one side workload alone and print its JSON record")
@@ -514,11 +514,13 @@ def cpu_baseline(seconds):
         return time.perf_counter() - t
 
     S = 1 << 14
+    run(S)  # warm-up: thread start, page faults
     dt = run(S)
-    S = int(min(S_BULK, max(S, S * seconds / max(dt, 1e-3))))
+    # one pass of about a tenth of the budget, repeated until the budget is spent
+    S = int(min(S_BULK, max(S, S * 0.1 * seconds / max(dt, 1e-3))))
     S = max(threads, S // threads * threads)
     reps, total_t, samples = 0, 0.0, 0
-    while total_t < seconds * 0.8 and reps < 20:
+    while total_t < seconds and reps < 1000:
         total_t += run(S)
         samples += len(gens) * S * N_BULK
         reps += 1
