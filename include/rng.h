@@ -199,9 +199,11 @@ int rng_xs256_placement(int placement, uint32_t *d_state, uint64_t n_streams, ui
 /* in one persistent launch captured in a HIP graph.  Each request is the   */
 /* slice [offset, offset + length) of one stream's serial sequence; the     */
 /* stream's state is advanced by offset + length.  Requests are cut into    */
-/* chunks of C samples whose start states come from jump-ahead (one jump    */
-/* per request, then a doubling tree with one uniform jump per chunk); a    */
-/* persistent kernel pulls 64-chunk tiles from an atomic counter.           */
+/* chunks of C samples whose start states come from jump-ahead: one jump    */
+/* per request, then a radix-16 tree (level l starts chunk q 16^l + r from  */
+/* chunk r, q < 16: at most four jumps by powers of two per chunk, one      */
+/* launch per level); a persistent kernel pulls 64-chunk tiles from an      */
+/* atomic counter.                                                          */
 /* ---------------------------------------------------------------------- */
 typedef struct {
     int32_t gen;            /* rng_gen_t */
@@ -234,8 +236,15 @@ int rng_batch_set(rng_batch_t *h, const rng_request_t *h_reqs, uint32_t n);
 int rng_batch_launch(rng_batch_t *h, void *stream);
 /* Persistent-kernel shape: wg lanes per workgroup (64..512), unroll
  * (samples per generation step) and chunk length C (a multiple of 64);
- * 0 keeps the current value.  Changing C requires a new rng_batch_set. */
+ * 0 keeps the current value.  chunk = RNG_BATCH_CHUNK_AUTO lets every plan
+ * choose C: the power of two in [256, 4096] (larger minimum for handles of
+ * more than 2^36 samples) that cuts the batch into about 2^17 chunks (as
+ * many 64-chunk tiles as the device holds waves), so that small batches
+ * still spread over the device.  A changed C applies to
+ * the last planned table at once (it is planned again). */
+#define RNG_BATCH_CHUNK_AUTO 0xFFFFFFFFu
 int rng_batch_set_shape(rng_batch_t *h, uint32_t wg, uint32_t unroll, uint32_t chunk);
+/* The current shape; chunk reads RNG_BATCH_CHUNK_AUTO in automatic mode. */
 int rng_batch_get_shape(rng_batch_t *h, uint32_t *wg, uint32_t *unroll, uint32_t *chunk);
 /* Time the planned batch under every persistent-kernel shape (wg x unroll)
  * and chunk length in {512, 1024, 2048, 4096}, reps launches each, and keep

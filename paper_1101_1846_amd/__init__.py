@@ -20,6 +20,7 @@ RNG_U32, RNG_F32 = 0, 1
 GENERATORS = {"MWC32": RNG_MWC32, "XS256": RNG_XS256, "XS32": RNG_XS32, "KISS": RNG_KISS,
               "MWC1616": RNG_MWC1616}
 DTYPES = {"u32": RNG_U32, "f32": RNG_F32}
+RNG_BATCH_CHUNK_AUTO = 0xFFFFFFFF
 RNG_XS_LDS_INDEXED, RNG_XS_LDS_UNROLLED, RNG_XS_VGPR = 0, 1, 2
 PLACEMENTS = {"lds_indexed": RNG_XS_LDS_INDEXED, "lds_unrolled": RNG_XS_LDS_UNROLLED, "vgpr": RNG_XS_VGPR}
 RNG_OK, RNG_EINVAL, RNG_ERANGE, RNG_ENOMEM, RNG_EHIP, RNG_ENODEV, RNG_EAGAIN = 0, -1, -2, -3, -4, -5, -6

@@ -1,6 +1,6 @@
 // rng_batch.cpp -- the batched path of the C ABI: plans a batch of
 // independent requests (chunking, grouping by generator and dtype, the
-// doubling-tree work lists), ships the plan through pinned host memory, and
+// radix-16 tree work lists), ships the plan through pinned host memory, and
 // replays one captured HIP graph per batch shape: counter reset, root jumps,
 // tree levels, persistent generation kernel.
 #include <hip/hip_runtime.h>
@@ -30,6 +30,7 @@ struct rng_batch {
     uint32_t max_requests = 0;
     uint64_t max_samples = 0;
     uint64_t C = 1024;
+    bool chunk_auto = false;  // C chosen per plan (RNG_BATCH_CHUNK_AUTO)
     uint32_t wg = 256, unroll = 8;
     uint64_t ws_words = 0;
     BatchHeader *d_hdr = nullptr, *h_hdr = nullptr;
@@ -51,6 +52,18 @@ struct rng_batch {
     std::vector<rng_request_t> last;  // last planned table, re-planned on a chunk change
     uint32_t n_seg = 0, n_blk = 0;    // level segments and block starts of the current plan
 };
+
+// Automatic chunk length: a power of two in [min, 4096] that cuts the batch
+// into about 2^17 chunks (2048 tiles of 64: the waves the device holds at
+// once), so that a small batch still spreads over the device.
+constexpr uint64_t kAutoChunkMax = 4096;
+constexpr uint64_t kAutoChunks = (uint64_t)1 << 17;
+static uint64_t auto_chunk_min(uint64_t max_samples)
+{
+    uint64_t c = 256;  // keeps the chunk capacity below 2^28
+    while (c < kAutoChunkMax && max_samples / c > ((uint64_t)1 << 28)) c *= 2;
+    return c;
+}
 
 static uint64_t chunk_capacity(const rng_batch *h, uint64_t C)
 {
@@ -195,10 +208,14 @@ int rng_batch_set_shape(rng_batch_t *h, uint32_t wg, uint32_t unroll, uint32_t c
     uint32_t w = wg ? wg : h->wg, u = unroll ? unroll : h->unroll;
     if (!shape_ok(w, u)) return fail(RNG_EINVAL, "batch launch shape wg=%u unroll=%u not available", w, u);
     if (chunk) {
-        if (chunk % kBatchTile) return fail(RNG_EINVAL, "chunk %u is not a multiple of %d", chunk, kBatchTile);
+        const bool autoc = chunk == RNG_BATCH_CHUNK_AUTO;
+        if (!autoc && chunk % kBatchTile)
+            return fail(RNG_EINVAL, "chunk %u is not a multiple of %d", chunk, kBatchTile);
         if (h->copy_pending) (void)hipEventSynchronize(h->copied);
-        if (int rc = alloc_ws(h, chunk)) return rc;
-        h->C = chunk;
+        const uint64_t cmin = autoc ? auto_chunk_min(h->max_samples) : chunk;
+        if (int rc = alloc_ws(h, cmin)) return rc;
+        h->chunk_auto = autoc;
+        h->C = autoc ? cmin : chunk;
         h->planned = false;  // the plan depends on the chunk length
         if (!h->last.empty()) {
             std::vector<rng_request_t> t = h->last;
@@ -216,7 +233,7 @@ int rng_batch_get_shape(rng_batch_t *h, uint32_t *wg, uint32_t *unroll, uint32_t
     std::lock_guard<std::mutex> lk(h->mu);
     *wg = h->wg;
     *unroll = h->unroll;
-    *chunk = (uint32_t)h->C;
+    *chunk = h->chunk_auto ? RNG_BATCH_CHUNK_AUTO : (uint32_t)h->C;
     return RNG_OK;
 }
 
@@ -233,7 +250,6 @@ int rng_batch_set(rng_batch_t *h, const rng_request_t *reqs, uint32_t n)
 static int plan(rng_batch_t *h, const rng_request_t *reqs, uint32_t n)
 {
     if (n > h->max_requests) return fail(RNG_ENOMEM, "%u requests > capacity %u", n, h->max_requests);
-    const uint64_t C = h->C;
     uint64_t total_samples = 0;
     for (uint32_t i = 0; i < n; ++i) {
         const rng_request_t &r = reqs[i];
@@ -248,6 +264,11 @@ static int plan(rng_batch_t *h, const rng_request_t *reqs, uint32_t n)
     if (total_samples > h->max_samples)
         return fail(RNG_ENOMEM, "batch of %llu samples > capacity %llu", (unsigned long long)total_samples,
                     (unsigned long long)h->max_samples);
+    if (h->chunk_auto) {
+        uint64_t c = auto_chunk_min(h->max_samples);
+        while (c < kAutoChunkMax && total_samples / (2 * c) >= kAutoChunks) c *= 2;
+        h->C = c;
+    }
     // The pinned staging buffers are about to be rewritten: wait for the
     // previous launch's copies to leave them.
     if (h->copy_pending) {
@@ -260,6 +281,7 @@ static int plan(rng_batch_t *h, const rng_request_t *reqs, uint32_t n)
     for (uint32_t i = 0; i < n; ++i) order[i] = i;
     auto key = [&](uint32_t i) { return reqs[i].gen * 2 + reqs[i].dtype; };
     std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return key(x) < key(y); });
+    const uint64_t C = h->C;
 
     BatchHeader &H = *h->h_hdr;
     std::memset(&H, 0, sizeof(H));
@@ -303,8 +325,9 @@ static int plan(rng_batch_t *h, const rng_request_t *reqs, uint32_t n)
     if (ws_off > h->ws_words) return fail(RNG_ENOMEM, "batch needs %llu workspace words > %llu",
                                           (unsigned long long)ws_off, (unsigned long long)h->ws_words);
     H.n_tiles = (uint32_t)tiles;
+    // radix-16 levels: 16^levels >= the largest request's chunk count
     uint32_t levels = 0;
-    while (((uint64_t)1 << levels) < max_chunks) ++levels;
+    while (((uint64_t)1 << (kRadixBits * levels)) < max_chunks) ++levels;
     if (levels > (uint32_t)kBatchMaxLevels) return fail(RNG_ERANGE, "a request needs more than 2^40 chunks");
     H.levels = levels;
     for (uint32_t g = 0; g < H.ngroups; ++g) H.has_xs256 |= H.groups[g].gen == (uint32_t)RNG_XS256;
@@ -317,14 +340,16 @@ static int plan(rng_batch_t *h, const rng_request_t *reqs, uint32_t n)
         LevelInfo &L = H.lvl[l];
         L.seg_off = S;
         L.blk_off = B;
-        L.pow = pow2 && lc + l < 64 ? lc + l : 0xFFFFFFFFu;
-        const uint64_t lo = (uint64_t)1 << l;
+        L.shift = kRadixBits * l;
+        L.pow = pow2 && lc + L.shift + kRadixBits <= 64 ? lc + L.shift : 0xFFFFFFFFu;
+        L.pad = 0;
+        const uint64_t lo = (uint64_t)1 << L.shift, hi = lo << kRadixBits;
         uint64_t acc = 0;
         for (uint32_t r = 0; r < n; ++r) {
             const uint64_t nc = h->h_reqs[r].nchunks;
             if (nc <= lo) continue;
             segs[S++] = make_uint2(r, (uint32_t)acc);
-            acc += std::min(nc, 2 * lo) - lo;
+            acc += std::min(nc, hi) - lo;
         }
         L.seg_n = S - L.seg_off;
         H.level_total[l] = (uint32_t)acc;

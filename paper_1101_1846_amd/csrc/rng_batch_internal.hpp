@@ -13,7 +13,7 @@
 namespace rngx {
 
 constexpr int kBatchMaxGroups = 10;   // 5 generators x 2 dtypes
-constexpr int kBatchMaxLevels = 40;   // doubling-tree levels (chunks per request < 2^40)
+constexpr int kBatchMaxLevels = 10;   // radix-16 tree levels (chunks per request < 2^40)
 constexpr int kBatchTile = 64;        // LDS tile depth of the batch kernel
 
 struct BatchReq {
@@ -38,17 +38,24 @@ struct BatchGroup {
     uint64_t ws_off;              // word offset of the group's [words][nchunks_pad] states
 };
 
-// Work list of one tree level.  Level l derives chunk j in [2^l, 2^(l+1)) of
-// every request with more than 2^l chunks from its chunk j - 2^l; those
-// requests are the level's segments, in table order, each with the exclusive
-// prefix of the work items before it.  Items are handled in blocks of 256;
-// the block start table gives the segment holding each block's first item,
-// so that a block needs only its 256 following segments.
+// Work list of one level of the radix-16 tree that gives every chunk its
+// start state.  Level l covers the chunks j in [16^l, 16^(l+1)) of every
+// request with more than 16^l chunks: with j = q 16^l + r (q in 1..15,
+// r < 16^l), chunk j starts where chunk r starts, jumped by q 16^l C samples
+// (level 0: chunk j < 16 from chunk 0, by j C).  Those requests are the
+// level's segments, in table order, each with the exclusive prefix of the
+// work items before it.  Items are handled in blocks of 256; the block start
+// table gives the segment holding each block's first item, so that a block
+// needs only its 256 following segments.
+constexpr int kRadixBits = 4;  // 16-way levels: up to 4 jumps by powers of two per chunk
+
 struct LevelInfo {
     uint32_t seg_off;  // first segment of the level in the segment array
-    uint32_t seg_n;    // segments (requests with more than 2^l chunks)
+    uint32_t seg_n;    // segments (requests with more than 16^l chunks)
     uint32_t blk_off;  // first entry of the level in the block start array
-    uint32_t pow;      // b with C * 2^l = 2^b, or 0xFFFFFFFF when C is no power of two
+    uint32_t shift;    // 4 l
+    uint32_t pow;      // b with C 16^l = 2^b, or 0xFFFFFFFF when C is no power of two
+    uint32_t pad;
 };
 
 // Per-batch header, rewritten before every launch (the captured graph only
@@ -58,8 +65,8 @@ struct BatchHeader {
     uint32_t n;           // requests
     uint32_t ngroups;
     uint32_t n_tiles;
-    uint32_t levels;      // doubling-tree levels used
-    uint32_t has_xs256;   // some group is XS256 (its level tables are staged in LDS)
+    uint32_t levels;      // radix-16 tree levels used
+    uint32_t has_xs256;   // some group is XS256 (its level's four tables are staged in LDS)
     uint32_t pad;
     uint32_t level_total[kBatchMaxLevels];  // work items per level
     LevelInfo lvl[kBatchMaxLevels];

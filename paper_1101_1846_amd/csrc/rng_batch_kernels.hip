@@ -1,5 +1,5 @@
 // rng_batch_kernels.hip -- kernels of the batched path: chunk start states by
-// jump-ahead (a root jump per request, then a doubling tree), and one
+// jump-ahead (a root jump per request, then a radix-16 tree), and one
 // persistent generation kernel whose wavefronts pull 64-chunk tiles from an
 // atomic counter until the batch is done.
 #include <hip/hip_runtime.h>
@@ -58,15 +58,16 @@ __global__ __launch_bounds__(256) void k_batch_root(BatchArgs a)
     }
 }
 
-// Level l of the doubling tree: chunk j in [2^l, min(2^(l+1), nchunks)) of
-// every request starts where chunk j - 2^l starts, jumped by C * 2^l.  A
-// block takes 256 consecutive work items: it loads the 256 segments from its
-// first item's segment on (a block spans at most 256 of them) into LDS, and
-// every thread finds its request there.  XS256 jumps by a power of two read
-// that power's lookup table, staged in LDS once per block.
+// Level l of the radix-16 tree: chunk j in [16^l, min(16^(l+1), nchunks)) of
+// every request, j = q 16^l + r, starts where chunk r starts, jumped by
+// q 16^l C.  A block takes 256 consecutive work items: it loads the 256
+// segments from its first item's segment on (a block spans at most 256 of
+// them) into LDS, and every thread finds its request there.  XS256 applies
+// the set bits of q with the lookup tables of M^(C 16^l 2^k), k < 4, staged
+// in LDS once per block (128 KiB: one block per CU).
 __global__ __launch_bounds__(256) void k_batch_level(BatchArgs a, uint32_t level)
 {
-    __shared__ uint4 s_t4[2048];
+    __shared__ uint4 s_t4[kRadixBits][2048];
     __shared__ uint32_t s_pre[256], s_req[256];
     const BatchHeader &h = *a.hdr;
     if (level >= h.levels) return;
@@ -74,13 +75,16 @@ __global__ __launch_bounds__(256) void k_batch_level(BatchArgs a, uint32_t level
     const uint32_t total = h.level_total[level];
     const uint32_t nblk = (total + 255) / 256;
     if (blockIdx.x >= nblk) return;
-    const bool staged = h.has_xs256 && L.pow < 64;
-    if (staged) stage_t4(s_t4, a.tab.xs256_t4 + (size_t)L.pow * 2048);
-    const uint32_t lo = 1u << level;
-    const uint64_t dist = h.C << level;
+    // pow is 0xFFFFFFFF when C is no power of two: compare without adding to it
+    const bool staged = h.has_xs256 && L.pow <= 64 - kRadixBits;
+    if (staged) {
+#pragma unroll
+        for (int k = 0; k < kRadixBits; ++k) stage_t4(s_t4[k], a.tab.xs256_t4 + (size_t)(L.pow + k) * 2048);
+    }
+    const uint32_t lo = 1u << L.shift;
     for (uint32_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
         const uint32_t k = a.blk_first[L.blk_off + blk] + threadIdx.x;
-        __syncthreads();  // the previous block's segments are consumed (and the table is staged)
+        __syncthreads();  // the previous block's segments are consumed (and the tables are staged)
         if (k < L.seg_n) {
             const uint2 sg = a.seg[L.seg_off + k];
             s_req[threadIdx.x] = sg.x;
@@ -99,17 +103,25 @@ __global__ __launch_bounds__(256) void k_batch_level(BatchArgs a, uint32_t level
         const uint32_t r = s_req[i];
         const BatchReq q = a.reqs[r];
         const BatchGroup &gr = h.groups[q.group];
-        const uint32_t c = q.chunk_base + lo + (t - s_pre[i]);
+        const uint32_t j = lo + (t - s_pre[i]);  // chunk within the request
+        const uint32_t rem = j & (lo - 1);       // the chunk it starts from
+        const uint32_t qd = j >> L.shift;        // in 1 .. 15
+        const uint32_t c = q.chunk_base + j;
         a.chunk_req[gr.tile_begin * 64 + c] = r;
         uint32_t *ws = a.ws + gr.ws_off;
         with_gen(gr.gen, [&]<class G>() {
             G g;
-            g.load(ws, gr.nchunks_pad, c - lo, a.tab);
+            g.load(ws, gr.nchunks_pad, q.chunk_base + rem, a.tab);
             if constexpr (G::kId == G_XS256) {
-                if (staged) g.jump_table(s_t4);
-                else g.jump(dist, a.tab);
+                if (staged) {
+#pragma unroll
+                    for (int b = 0; b < kRadixBits; ++b)
+                        if ((qd >> b) & 1) g.jump_table(s_t4[b]);
+                } else {
+                    g.jump((uint64_t)(j - rem) * h.C, a.tab);
+                }
             } else {
-                g.jump(dist, a.tab);
+                g.jump((uint64_t)(j - rem) * h.C, a.tab);
             }
             g.store(ws, gr.nchunks_pad, c);
         });

@@ -280,6 +280,9 @@ int rng_server_create(const rng_server_config_t *cfg, rng_server_t **out)
             (e = hipEventCreateWithFlags(&s.ev, hipEventDisableTiming)) != hipSuccess)
             rc = hip_fail(e, "server stream/event");
         if (!rc) rc = rng_batch_create(cfg->max_batch_requests, cfg->max_batch_samples, &s.batch);
+        // every batch picks its chunk length, so that a lone small request
+        // still spreads over the device
+        if (!rc && s.batch) rc = rng_batch_set_shape(s.batch, 0, 0, RNG_BATCH_CHUNK_AUTO);
         h->slots.push_back(s);
     }
     if (!rc && (e = hipDeviceSynchronize()) != hipSuccess) rc = hip_fail(e, "hipDeviceSynchronize");

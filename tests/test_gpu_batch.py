@@ -157,6 +157,36 @@ def test_batch_chunk_lengths(rng, torch, oracle, chunk):
         rng.rng_batch_destroy(h)
 
 
+def test_batch_tree_path(rng, torch, oracle):
+    """More than 2^15 chunks (64-sample chunks over about 3e6 samples): the chunk
+    start states come from the doubling tree rather than direct jumps."""
+    m = Mix(rng, torch, oracle, 300, seed=5, max_len=20000)
+    assert sum(-(-int(n) // 64) for n in m.length) > (1 << 15)
+    h = rng.rng_batch_create(1000, 1 << 24)
+    try:
+        rng.rng_batch_set_shape(h, 0, 0, 64)
+        rng.rng_batch_set(h, m.requests())
+        rng.rng_batch_launch(h)
+        m.check()
+    finally:
+        rng.rng_batch_destroy(h)
+
+
+@pytest.mark.parametrize("n,max_len", [(1, 1 << 17), (5, 1 << 20), (300, 20000)])
+def test_batch_auto_chunk(rng, torch, oracle, n, max_len):
+    """Automatic chunk length: every plan picks C from the batch's size."""
+    m = Mix(rng, torch, oracle, n, seed=6 + n, max_len=max_len)
+    h = rng.rng_batch_create(1000, 1 << 24)
+    try:
+        rng.rng_batch_set_shape(h, 0, 0, rng.RNG_BATCH_CHUNK_AUTO)
+        assert rng.rng_batch_get_shape(h)[2] == rng.RNG_BATCH_CHUNK_AUTO
+        rng.rng_batch_set(h, m.requests())
+        rng.rng_batch_launch(h)
+        m.check()
+    finally:
+        rng.rng_batch_destroy(h)
+
+
 def test_batch_graph_replays(rng, torch, oracle):
     """The same plan launched three times, with eager library work and a
     synchronisation between replays: replay k must give pass k of every stream."""
