@@ -146,7 +146,7 @@ int rng_generate_split(int g, const uint32_t *d_state_one, uint64_t total, uint6
  * rng_generate_split, computed the other way round.  With T = min(n_threads,
  * total) threads, thread j emits numbers j, j + T, j + 2T, ... of the serial
  * sequence, so d_out[i] is number i and every wave stores 64 consecutive
- * numbers.  Thread j starts at the state after j steps (a doubling tree of
+ * numbers.  Thread j starts at the state after j steps (a radix-16 tree of
  * jumps), steps once, and then advances T steps per number with the
  * generator's T-step map: one modular multiply per MWC word, a 32x32 GF(2)
  * product for xorshift32, a 256x256 one for XS256 (through a 4-bit table of

@@ -1,8 +1,8 @@
 // leapfrog.hip -- leapfrog parallelisation of one sequence (Sec. II.A.4):
 // thread j of T emits R_j, R_{j+T}, R_{j+2T}, ..., so that number i of the
 // sequence lands at out[i] and every wave stores 64 consecutive numbers.
-// Each thread starts at state_j (a doubling tree of uniform jumps, as for
-// sequence splitting), steps once, and then leaps T steps per number with the
+// Each thread starts at state_j (a radix-16 tree of jumps, as for sequence
+// splitting), steps once, and then leaps T steps per number with the
 // generator's T-step map:
 //   MWC32    z <- (a^T mod m) z mod m         one fold-domain multiply (eq. (4))
 //   MWC1616  z, w <- a_i^T z mod m_i           two; constants from the state's multipliers
@@ -221,10 +221,10 @@ int rng_generate_leapfrog(int g, const uint32_t *d_state_one, uint64_t total, ui
     if (int rc = device_tables(&tab)) return rc;
     uint32_t *ws = (uint32_t *)d_workspace;
     uint32_t *dconst = (uint32_t *)((char *)d_workspace + align256(T * gen_words(g) * 4));
-    // thread j starts at state_j: state_0 copied to slot 0, then a doubling tree
+    // thread j starts at state_j: state_0 copied to slot 0, then a radix-16 tree
     int rc = check_launch(dispatch_state_copy(g, d_state_one, 1, 0, ws, T, 0, st), "leapfrog: init");
-    for (uint64_t lo = 1; !rc && lo < T; lo *= 2)
-        rc = check_launch(dispatch_tree_level(g, ws, T, lo, lo, tab, st), "leapfrog: tree level");
+    for (uint32_t shift = 0; !rc && ((uint64_t)1 << shift) < T; shift += 4)
+        rc = check_launch(dispatch_tree_level(g, ws, T, shift, 1, tab, st), "leapfrog: tree level");
     if (rc) return rc;
     if (g == RNG_MWC1616 || g == RNG_KISS) {
         const uint32_t wa1 = g == RNG_MWC1616 ? 2 : 4;

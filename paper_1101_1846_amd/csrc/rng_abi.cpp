@@ -214,10 +214,10 @@ int dispatch_skip(int g, uint32_t *st, uint64_t S, uint64_t k, const DevTables &
     RNGX_GEN_SWITCH(g, launch_skip_t<G>(st, S, k, tab, s))
 }
 
-int dispatch_tree_level(int g, uint32_t *ws, uint64_t T, uint64_t lo, uint64_t dist, const DevTables &tab,
+int dispatch_tree_level(int g, uint32_t *ws, uint64_t T, uint32_t shift, uint64_t unit, const DevTables &tab,
                         hipStream_t s)
 {
-    RNGX_GEN_SWITCH(g, launch_tree_level_t<G>(ws, T, lo, dist, tab, s))
+    RNGX_GEN_SWITCH(g, launch_tree_level_t<G>(ws, T, shift, unit, tab, s))
 }
 
 int dispatch_state_copy(int g, const uint32_t *src, uint64_t ss, uint64_t si, uint32_t *dst, uint64_t ds,
@@ -436,10 +436,11 @@ int rng_generate_split(int g, const uint32_t *d_state_one, uint64_t total, uint6
     uint32_t *ws = (uint32_t *)d_workspace;
     int rc = check_launch(dispatch_state_copy(g, d_state_one, 1, 0, ws, T, 0, st), "split: init");
     if (rc) return rc;
-    for (uint64_t lo = 1; lo < T; lo *= 2) {
-        uint64_t dist;
-        if (mul_overflows(C, lo, &dist)) return fail(RNG_ERANGE, "jump distance overflows");
-        rc = check_launch(dispatch_tree_level(g, ws, T, lo, dist, tab, st), "split: tree level");
+    // radix-16 tree: level l starts threads [16^l, 16^(l+1)) from threads below 16^l
+    uint64_t far;
+    if (mul_overflows(C, T, &far)) return fail(RNG_ERANGE, "jump distance overflows");
+    for (uint32_t shift = 0; ((uint64_t)1 << shift) < T; shift += 4) {
+        rc = check_launch(dispatch_tree_level(g, ws, T, shift, C, tab, st), "split: tree level");
         if (rc) return rc;
     }
     const uint64_t rem = total - (T - 1) * C;  // samples of the last thread

@@ -74,10 +74,10 @@ static uint64_t chunk_capacity(const rng_batch *h, uint64_t C)
 static uint64_t seg_capacity(const rng_batch *h) { return (uint64_t)kBatchMaxLevels * h->max_requests; }
 
 // Block starts of all levels: the levels' work items sum to fewer than the
-// chunks, so sum(ceil(items / 256)) <= chunks / 256 + levels.
+// chunks, so sum(ceil(items / kLevelWG)) <= chunks / kLevelWG + levels.
 static uint64_t lvl_capacity(const rng_batch *h, uint64_t C)
 {
-    return 2 * seg_capacity(h) + chunk_capacity(h, C) / 256 + kBatchMaxLevels + 1;
+    return 2 * seg_capacity(h) + chunk_capacity(h, C) / kLevelWG + kBatchMaxLevels + 1;
 }
 
 // Sizes the chunk workspace, the chunk-to-request map and the level work
@@ -354,7 +354,7 @@ static int plan(rng_batch_t *h, const rng_request_t *reqs, uint32_t n)
         L.seg_n = S - L.seg_off;
         H.level_total[l] = (uint32_t)acc;
         uint32_t k = 0;
-        for (uint64_t t0 = 0; t0 < acc; t0 += 256) {
+        for (uint64_t t0 = 0; t0 < acc; t0 += kLevelWG) {
             while (k + 1 < L.seg_n && segs[L.seg_off + k + 1].y <= t0) ++k;
             blks[B++] = k;
         }
@@ -398,7 +398,7 @@ int rng_batch_launch(rng_batch_t *h, void *stream)
         if (batch_gen_occupancy((int)h->wg, (int)h->unroll, &per_cu) || per_cu <= 0) per_cu = 1;
         const unsigned gen_grid = (unsigned)(h->num_cu * per_cu);
         const uint64_t cap = chunk_capacity(h, h->C);
-        const unsigned level_grid = (unsigned)std::min<uint64_t>((cap + 255) / 256, 1024);
+        const unsigned level_grid = (unsigned)std::min<uint64_t>((cap + kLevelWG - 1) / kLevelWG, 256);
         const BatchArgs a = make_args(h, tab);
         rng_batch::Graph g{H.levels, h->wg, h->unroll, nullptr, nullptr};
         // Recorded on the handle's own stream (the caller's may be the null

@@ -44,10 +44,11 @@ struct BatchGroup {
 // r < 16^l), chunk j starts where chunk r starts, jumped by q 16^l C samples
 // (level 0: chunk j < 16 from chunk 0, by j C).  Those requests are the
 // level's segments, in table order, each with the exclusive prefix of the
-// work items before it.  Items are handled in blocks of 256; the block start
-// table gives the segment holding each block's first item, so that a block
-// needs only its 256 following segments.
-constexpr int kRadixBits = 4;  // 16-way levels: up to 4 jumps by powers of two per chunk
+// work items before it.  Items are handled in blocks of kLevelWG; the block
+// start table gives the segment holding each block's first item, so that a
+// block needs only its kLevelWG following segments.
+constexpr int kRadixBits = 4;    // 16-way levels: up to 4 jumps by powers of two per chunk
+constexpr int kLevelWG = 1024;   // lanes (and work items) per level workgroup
 
 struct LevelInfo {
     uint32_t seg_off;  // first segment of the level in the segment array

@@ -60,20 +60,20 @@ __global__ __launch_bounds__(256) void k_batch_root(BatchArgs a)
 
 // Level l of the radix-16 tree: chunk j in [16^l, min(16^(l+1), nchunks)) of
 // every request, j = q 16^l + r, starts where chunk r starts, jumped by
-// q 16^l C.  A block takes 256 consecutive work items: it loads the 256
-// segments from its first item's segment on (a block spans at most 256 of
-// them) into LDS, and every thread finds its request there.  XS256 applies
-// the set bits of q with the lookup tables of M^(C 16^l 2^k), k < 4, staged
-// in LDS once per block (128 KiB: one block per CU).
-__global__ __launch_bounds__(256) void k_batch_level(BatchArgs a, uint32_t level)
+// q 16^l C.  A block takes kLevelWG consecutive work items: it loads the
+// kLevelWG segments from its first item's segment on (a block spans at most
+// that many) into LDS, and every thread finds its request there.  XS256
+// applies the set bits of q with the lookup tables of M^(C 16^l 2^k), k < 4,
+// staged in LDS once per block (128 KiB: one 1024-lane block per CU).
+__global__ __launch_bounds__(kLevelWG) void k_batch_level(BatchArgs a, uint32_t level)
 {
     __shared__ uint4 s_t4[kRadixBits][2048];
-    __shared__ uint32_t s_pre[256], s_req[256];
+    __shared__ uint32_t s_pre[kLevelWG], s_req[kLevelWG];
     const BatchHeader &h = *a.hdr;
     if (level >= h.levels) return;
     const LevelInfo L = h.lvl[level];
     const uint32_t total = h.level_total[level];
-    const uint32_t nblk = (total + 255) / 256;
+    const uint32_t nblk = (total + kLevelWG - 1) / kLevelWG;
     if (blockIdx.x >= nblk) return;
     // pow is 0xFFFFFFFF when C is no power of two: compare without adding to it
     const bool staged = h.has_xs256 && L.pow <= 64 - kRadixBits;
@@ -94,11 +94,11 @@ __global__ __launch_bounds__(256) void k_batch_level(BatchArgs a, uint32_t level
             s_pre[threadIdx.x] = 0xFFFFFFFFu;
         }
         __syncthreads();
-        const uint32_t t = blk * 256 + threadIdx.x;
+        const uint32_t t = blk * kLevelWG + threadIdx.x;
         if (t >= total) continue;
         uint32_t i = 0;  // largest i with s_pre[i] <= t (s_pre[0] <= t by construction)
 #pragma unroll
-        for (uint32_t step = 128; step; step >>= 1)
+        for (uint32_t step = kLevelWG / 2; step; step >>= 1)
             if (s_pre[i + step] <= t) i += step;
         const uint32_t r = s_req[i];
         const BatchReq q = a.reqs[r];
@@ -269,7 +269,7 @@ int launch_batch_root(const BatchArgs &a, uint32_t max_requests, hipStream_t s)
 
 int launch_batch_level(const BatchArgs &a, uint32_t level, unsigned grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_batch_level, dim3(grid), dim3(256), 0, s, a, level);
+    hipLaunchKernelGGL(k_batch_level, dim3(grid), dim3(kLevelWG), 0, s, a, level);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

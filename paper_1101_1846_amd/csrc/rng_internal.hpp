@@ -62,7 +62,7 @@ int launch_seed_t(uint64_t seed, uint64_t first, uint64_t S, uint32_t *st, const
 template <class G>
 int launch_skip_t(uint32_t *st, uint64_t S, uint64_t k, const DevTables &tab, hipStream_t stream);
 template <class G>
-int launch_tree_level_t(uint32_t *ws, uint64_t T, uint64_t lo, uint64_t dist, const DevTables &tab,
+int launch_tree_level_t(uint32_t *ws, uint64_t T, uint32_t shift, uint64_t unit, const DevTables &tab,
                         hipStream_t stream);
 template <class G>
 int launch_state_copy_t(const uint32_t *src, uint64_t ss, uint64_t si, uint32_t *dst, uint64_t ds,

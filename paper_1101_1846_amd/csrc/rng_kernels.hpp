@@ -52,35 +52,53 @@ __global__ __launch_bounds__(256) void k_skip(uint32_t *__restrict__ st, uint64_
     g.store(st, S, s);
 }
 
-// One level of the doubling tree used by sequence splitting: thread t in
-// [lo, min(2 lo, T)) starts where thread t - lo starts plus dist samples.
-// For XS256 with a power-of-two distance, each workgroup first stages that
-// power's 32 KiB lookup table in LDS; the grid then strides over the level.
+// One level of the radix-16 tree that starts the threads of a split
+// sequence: thread t in [16^l, min(16^(l+1), T)), t = q 16^l + r with q in
+// 1..15, starts where thread r starts, jumped by q 16^l unit samples.  For
+// XS256 with a power-of-two unit, each workgroup stages the lookup tables of
+// M^(unit 16^l 2^k), k < 4, in LDS (128 KiB: one 1024-lane workgroup per CU,
+// 16 waves sharing them) and applies the set bits of q; the grid strides over
+// the level.
+constexpr int kTreeWG = 1024;
+
 template <class G>
-__global__ __launch_bounds__(256) void k_tree_level(uint32_t *__restrict__ ws, uint64_t T, uint64_t lo,
-                                                    uint64_t dist, DevTables tab)
+__global__ __launch_bounds__(kTreeWG) void k_tree_level(uint32_t *__restrict__ ws, uint64_t T, uint32_t shift,
+                                                        uint64_t unit, DevTables tab)
 {
-    const uint64_t n = min(lo, T - lo);
+    const uint64_t lo = (uint64_t)1 << shift;
+    const uint64_t hi = min(lo << 4, T);
+    const uint64_t n = hi - lo;
+    const uint64_t first = (uint64_t)blockIdx.x * kTreeWG + threadIdx.x, stride = (uint64_t)gridDim.x * kTreeWG;
     if constexpr (G::kId == G_XS256) {
-        __shared__ uint4 s_t4[2048];
-        const bool staged = (dist & (dist - 1)) == 0;
+        __shared__ uint4 s_t4[4][2048];
+        const uint32_t b0 = (uint32_t)__builtin_ctzll(unit) + shift;
+        const bool staged = (unit & (unit - 1)) == 0 && b0 <= 60;
         if (staged) {
-            stage_t4(s_t4, tab.xs256_t4 + (size_t)__builtin_ctzll(dist) * 2048);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) stage_t4(s_t4[k], tab.xs256_t4 + (size_t)(b0 + k) * 2048);
             __syncthreads();
         }
-        for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+        for (uint64_t i = first; i < n; i += stride) {
+            const uint64_t t = lo + i, r = t & (lo - 1);
             G g;
-            g.load(ws, T, i, tab);
-            if (staged) g.jump_table(s_t4);
-            else g.jump(dist, tab);
-            g.store(ws, T, lo + i);
+            g.load(ws, T, r, tab);
+            if (staged) {
+                const uint32_t q = (uint32_t)(t >> shift);
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if ((q >> k) & 1) g.jump_table(s_t4[k]);
+            } else {
+                g.jump((t - r) * unit, tab);
+            }
+            g.store(ws, T, t);
         }
     } else {
-        for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+        for (uint64_t i = first; i < n; i += stride) {
+            const uint64_t t = lo + i, r = t & (lo - 1);
             G g;
-            g.load(ws, T, i, tab);
-            g.jump(dist, tab);
-            g.store(ws, T, lo + i);
+            g.load(ws, T, r, tab);
+            g.jump((t - r) * unit, tab);
+            g.store(ws, T, t);
         }
     }
 }
@@ -454,14 +472,14 @@ int launch_skip_t(uint32_t *st, uint64_t S, uint64_t k, const DevTables &tab, hi
 }
 
 template <class G>
-int launch_tree_level_t(uint32_t *ws, uint64_t T, uint64_t lo, uint64_t dist, const DevTables &tab,
+int launch_tree_level_t(uint32_t *ws, uint64_t T, uint32_t shift, uint64_t unit, const DevTables &tab,
                         hipStream_t stream)
 {
-    // XS256 workgroups each stage a 32 KiB table: at most 2 per CU, striding
-    const uint64_t n = min(lo, T - lo);
-    const unsigned cap = G::kId == G_XS256 ? 512 : 8192, blocks = grid_for(n, 256);
-    hipLaunchKernelGGL(k_tree_level<G>, dim3(blocks < cap ? blocks : cap), dim3(256), 0, stream, ws, T, lo, dist,
-                       tab);
+    // XS256 workgroups each stage 128 KiB of tables: one per CU, striding
+    const uint64_t lo = (uint64_t)1 << shift, hi = (lo << 4) < T ? (lo << 4) : T;
+    const unsigned cap = G::kId == G_XS256 ? 256 : 2048, blocks = grid_for(hi - lo, kTreeWG);
+    hipLaunchKernelGGL(k_tree_level<G>, dim3(blocks < cap ? blocks : cap), dim3(kTreeWG), 0, stream, ws, T, shift,
+                       unit, tab);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -555,7 +573,7 @@ int launch_fused_pi_t(const FusedArgs &a, hipStream_t stream)
     template int launch_seed_t<G>(uint64_t, uint64_t, uint64_t, uint32_t *, const DevTables &,        \
                                   hipStream_t);                                                        \
     template int launch_skip_t<G>(uint32_t *, uint64_t, uint64_t, const DevTables &, hipStream_t);    \
-    template int launch_tree_level_t<G>(uint32_t *, uint64_t, uint64_t, uint64_t, const DevTables &,  \
+    template int launch_tree_level_t<G>(uint32_t *, uint64_t, uint32_t, uint64_t, const DevTables &,  \
                                         hipStream_t);                                                  \
     template int launch_state_copy_t<G>(const uint32_t *, uint64_t, uint64_t, uint32_t *, uint64_t,  \
                                         uint64_t, hipStream_t);                                        \
