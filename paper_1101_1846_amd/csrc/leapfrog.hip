@@ -6,7 +6,7 @@
 // generator's T-step map:
 //   MWC32    z <- (a^T mod m) z mod m         one fold-domain multiply (eq. (4))
 //   MWC1616  z, w <- a_i^T z mod m_i           two; constants from the state's multipliers
-//   XS32     y <- M^T y                        32x32 GF(2) product
+//   XS32     y <- M^T y                        32x32 GF(2) product, byte tables in LDS
 //   XS256    v <- M^T v                        256x256 GF(2) product, 4-bit table in LDS
 //   KISS     MWC1616 and XS32 parts as above, LCG jcong <- A_T jcong + C_T
 // The constants that depend only on T come from the host's jump tables; the
@@ -27,12 +27,14 @@ namespace {
 constexpr uint64_t kConstBytes = 256;                 // MWC16 fold constants
 constexpr uint64_t kColBytes = 256 * 8 * 4;           // XS256 columns of M^T
 constexpr uint64_t kTableBytes = 2048 * 16;           // XS256 4-bit table of M^T
+constexpr uint64_t kByteTableBytes = 4 * 256 * 4;     // xorshift32 byte tables of M^T
 
 uint64_t align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
 
 struct LeapArgs {
     const uint32_t *ws;      // [W][T] thread start states (state_j)
-    const uint32_t *dconst;  // device-built constants: [0], [1] MWC16 fold constants; XS256 table at +kConstBytes+kColBytes
+    const uint32_t *dconst;  // device-built constants: [0], [1] MWC16 fold constants; XS256 table at
+                             // +kConstBytes+kColBytes; xorshift32 byte tables at +kConstBytes
     uint64_t T, total;
     uint32_t *out;           // [total]
     uint32_t *final_state;   // [W]
@@ -91,8 +93,27 @@ __global__ __launch_bounds__(256) void k_leap_xs256_table(const uint32_t *cols, 
     t4[q] = make_uint4(r[0], r[1], r[2], r[3]);
 }
 
+// Byte tables of the xorshift32 M^T: entry p * 256 + v is the XOR of columns
+// 8p + k over the set bits k of v, so M^T y is the XOR of the four entries
+// selected by the bytes of y.
+__global__ __launch_bounds__(256) void k_leap_xs32_table(LeapArgs a, uint32_t *t8)
+{
+    const uint32_t e = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t p = e >> 8, v = e & 255;
+    uint32_t r = 0;
+    for (int k = 0; k < 8; ++k)
+        if ((v >> k) & 1) r ^= a.xs32[8 * p + k];
+    t8[e] = r;
+}
+
+__device__ __forceinline__ uint32_t xs32_bytes(const uint32_t *t8, uint32_t y)
+{
+    return xor3(t8[y & 255], t8[256 + ((y >> 8) & 255)], t8[512 + ((y >> 16) & 255)]) ^ t8[768 + (y >> 24)];
+}
+
 template <class G>
-__device__ __forceinline__ void leap(G &g, const LeapArgs &a, uint32_t m16a, uint32_t m16b, const uint4 *t4)
+__device__ __forceinline__ void leap(G &g, const LeapArgs &a, uint32_t m16a, uint32_t m16b, const uint4 *t4,
+                                     const uint32_t *t8)
 {
     if constexpr (G::kId == G_MWC32) {
         uint64_t z = (uint64_t)g.c << 32 | g.x;
@@ -102,14 +123,14 @@ __device__ __forceinline__ void leap(G &g, const LeapArgs &a, uint32_t m16a, uin
     } else if constexpr (G::kId == G_XS256) {
         gf2_apply256_t4(t4, g.v);
     } else if constexpr (G::kId == G_XS32) {
-        g.y = gf2_apply32(a.xs32, g.y);
+        g.y = xs32_bytes(t8, g.y);
     } else if constexpr (G::kId == G_MWC1616) {
         g.z = mwc16_mulmod(g.z, m16a, g.a1);
         g.w = mwc16_mulmod(g.w, m16b, g.a2);
     } else {
         g.z = mwc16_mulmod(g.z, m16a, g.a1);
         g.w = mwc16_mulmod(g.w, m16b, g.a2);
-        g.jsr = gf2_apply32(a.xs32, g.jsr);
+        g.jsr = xs32_bytes(t8, g.jsr);
         g.jcong = a.lcg_a * g.jcong + a.lcg_c;
     }
 }
@@ -120,9 +141,16 @@ template <class G, int DT>
 __global__ __launch_bounds__(256) void k_leapfrog(LeapArgs a)
 {
     constexpr bool kTable = G::kId == G_XS256;
+    constexpr bool kBytes = G::kId == G_XS32 || G::kId == G_KISS;
     __shared__ uint4 s_t4[kTable ? 2048 : 1];
+    __shared__ uint32_t s_t8[kBytes ? 1024 : 1];
     if constexpr (kTable) {
         stage_t4(s_t4, (const uint4 *)((const char *)a.dconst + kConstBytes + kColBytes));
+        __syncthreads();
+    }
+    if constexpr (kBytes) {
+        const uint32_t *t8 = (const uint32_t *)((const char *)a.dconst + kConstBytes);
+        for (uint32_t i = threadIdx.x; i < 1024; i += 256) s_t8[i] = t8[i];
         __syncthreads();
     }
     const uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x;
@@ -140,7 +168,7 @@ __global__ __launch_bounds__(256) void k_leapfrog(LeapArgs a)
         if (pos == a.total - 1) g.store(a.final_state, 1, 0);
         pos += a.T;
         if (pos >= a.total) break;
-        leap(g, a, m16a, m16b, s_t4);
+        leap(g, a, m16a, m16b, s_t4, s_t8);
         u = g.last();
     }
 }
@@ -188,7 +216,9 @@ int rng_leapfrog_workspace_bytes(int g, uint64_t n_threads, uint64_t *bytes)
     if (check_gen(g)) return RNG_EINVAL;
     if (!bytes) return fail(RNG_EINVAL, "bytes is NULL");
     if (n_threads > ((uint64_t)1 << 36)) return fail(RNG_ERANGE, "n_threads above 2^36");
-    *bytes = align256(n_threads * gen_words(g) * 4) + kConstBytes + (g == RNG_XS256 ? kColBytes + kTableBytes : 0);
+    const bool bytes_t = g == RNG_XS32 || g == RNG_KISS;
+    *bytes = align256(n_threads * gen_words(g) * 4) + kConstBytes + (g == RNG_XS256 ? kColBytes + kTableBytes : 0) +
+             (bytes_t ? kByteTableBytes : 0);
     return RNG_OK;
 }
 
@@ -247,6 +277,10 @@ int rng_generate_leapfrog(int g, const uint32_t *d_state_one, uint64_t total, ui
     a.final_state = d_final_state;
     a.tab = tab;
     host_leap_constants(T, a);
+    if (g == RNG_XS32 || g == RNG_KISS) {
+        hipLaunchKernelGGL(k_leap_xs32_table, dim3(4), dim3(256), 0, st, a, (uint32_t *)((char *)dconst + kConstBytes));
+        if (hipGetLastError() != hipSuccess) return fail(RNG_EHIP, "leapfrog: xorshift32 tables");
+    }
     switch (g) {
     case RNG_MWC32: rc = launch_leapfrog<GenMWC32>(t, a, st); break;
     case RNG_XS256: rc = launch_leapfrog<GenXS256>(t, a, st); break;
