@@ -43,6 +43,10 @@
  *  - Device tables (multiplier table, jump-ahead power tables) are built on
  *    the host and uploaded once per device, lazily on first use or by
  *    rng_init(); they are owned by the library until rng_shutdown().
+ *  - rng_seed, rng_generate(_ex), rng_skip, rng_generate_split and
+ *    rng_fused_pi only launch kernels on the given stream once the device
+ *    tables exist, so they may be captured into a HIP graph after rng_init()
+ *    (call each shape once outside the capture first).
  */
 #ifndef RNG_MI355X_H
 #define RNG_MI355X_H
