@@ -43,7 +43,7 @@ extern "C" int rng_calibrate_valu(int op, double *lane_ops_per_s, void *stream)
     (void)hipGetDevice(&dev);
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
-    const unsigned blocks = (unsigned)cus * 16;  // 16 waves of 64 per SIMD... 4 x 256-lane groups per SIMD
+    const unsigned blocks = (unsigned)cus * 16;  // 16 workgroups of 256 lanes per CU (several rounds of 8 waves per SIMD)
     const uint32_t iters = 4096;
     hipStream_t st = (hipStream_t)stream;
     uint32_t *out = nullptr;
