@@ -266,6 +266,9 @@ int rng_batch_destroy(rng_batch_t *h);
 /* device), and stamps each request's completion.  Requests for the same   */
 /* stream are served in arrival order, so request i of a stream returns the */
 /* samples [L_0 + ... + L_{i-1}, + L_i) of that stream's serial sequence.   */
+/* While batches are in flight the worker polls their events in a loop (it  */
+/* keeps one host core busy, for latency); it sleeps when none are.  Every  */
+/* batch picks its chunk length automatically (RNG_BATCH_CHUNK_AUTO).       */
 /* ---------------------------------------------------------------------- */
 typedef struct {
     uint64_t n_streams;            /* resident streams; stream s runs gens[s % n_gens] */
@@ -298,10 +301,15 @@ int rng_server_submit(rng_server_t *h, uint64_t stream_id, uint64_t length, int 
 int rng_server_poll(rng_server_t *h, uint64_t ticket, int *done, void **d_out);
 /* Return a completed request's output memory to the pool. */
 int rng_server_release(rng_server_t *h, uint64_t ticket);
-/* Block until every submitted request has completed. */
+/* Block until every submitted request has completed.  Admission needs free
+ * output memory: with auto_release = 0, requests beyond the pool complete
+ * only as the caller releases earlier outputs (from another thread), so a
+ * caller that drains without releasing waits for ever once the pool fills. */
 int rng_server_drain(rng_server_t *h);
 /* Copy one idle stream's resident state to the host ([words] uint32): the
- * resident states are the server's checkpoint. */
+ * resident states are the server's checkpoint.  RNG_EAGAIN while a request
+ * for that stream is in flight; a request submitted concurrently may still
+ * overtake the copy, so read states with no request pending for them. */
 int rng_server_read_state(rng_server_t *h, uint64_t stream_id, uint32_t *h_state);
 int rng_server_stats(rng_server_t *h, rng_server_stats_t *st);
 int rng_server_reset_stats(rng_server_t *h);
