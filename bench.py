@@ -55,8 +55,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU; --gpus %d is not supported "
-              "(streams shard across GPUs with no exchange; see DESIGN.md)" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU; --gpus %d is not supported "
+              "(streams shard by range across GPUs with no exchange)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
