@@ -44,7 +44,7 @@ def parse():
     p.add_argument("--no-extra", action="store_true", help="skip the side workloads")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-tune", action="store_true", help="keep the library's default launch shapes")
-    p.add_argument("--only", choices=["batched", "served", "split", "fused", "small", "placement"],
+    p.add_argument("--only", choices=["batched", "served", "split", "fused", "small", "placement", "fold"],
                    help="run one side workload alone and print its JSON record")
     p.add_argument("--profile", metavar="GEN_DTYPE",
                    help="counter-collection mode: a 1 GiB device copy (calibration) then 3 launches of "
@@ -251,7 +251,8 @@ def _time(torch, fn, reps):
 
 def side_workloads(torch, R, dev, stream, only=None):
     """Every workload besides the timed step, or only the one named."""
-    parts = {"small": small_workloads, "split": split_workload, "placement": placement_workload}
+    parts = {"small": small_workloads, "split": split_workload, "placement": placement_workload,
+             "fold": fold_workload}
     res = {}
     if only in parts:
         res.update(parts[only](torch, R, dev))
@@ -271,6 +272,7 @@ def side_workloads(torch, R, dev, stream, only=None):
     res["served"] = served_workload(R, res["batched_10k_requests"]["single_large_call_GSamples_s"])
     res.update(fused_workload(torch, R, dev))
     res.update(placement_workload(torch, R, dev))
+    res.update(fold_workload(torch, R, dev))
     torch.cuda.empty_cache()
     return res
 
@@ -340,6 +342,41 @@ def split_workload(torch, R, dev):
 # implicit, explicit and register forms), quoted for context only: other hardware, its own sizes.
 PAPER_TABLE2_RATE = {"lds_indexed": (4.4, 4.8), "lds_unrolled": (8.1, 13.8), "vgpr": (12.5, 14.5)}
 XS256_USEFUL_OPS = 18  # useful operations per XorShift number (11 XORs, 7 shifts)
+
+
+# Useful operations per number (eq. (9)'s n_ops): the paper's counts for its MWC (10), XorShift (18) and
+# KISS (18); the counterparts here for the base-2^32 MWC (one 32x32+32 -> 64 multiply-add: 2) and xorshift32 (6).
+USEFUL_OPS = {"MWC32": 2, "MWC1616": 10, "XS32": 6, "XS256": 18, "KISS": 18}
+# The paper's GTX280 rates without write-back (integer, uniform), GSamples/s: context only.
+PAPER_NO_WRITEBACK = {"MWC1616": (37.5, 23.6), "XS256": (14.5, 12.9), "KISS": (19.1, 10.3)}
+
+
+def fold_workload(torch, R, dev):
+    """Every generator without write-back (2^20 streams x 2^12 numbers, per-stream XOR
+    only) and with it (the same streams, 2^20 x 256 store mode), uint32 and FP32."""
+    S = S_BULK
+    res = {}
+    fold = torch.zeros(S, dtype=torch.int32, device=dev)
+    out = torch.empty(S * N_BULK, dtype=torch.int32, device=dev)
+    for name, g in R.GENERATORS.items():
+        st = torch.empty((R.rng_state_words(g), S), dtype=torch.int32, device=dev)
+        R.rng_seed(g, 7, 0, S, st)
+        row = {}
+        for dname, d in R.DTYPES.items():
+            n = 1 << 12
+            ms = _time(torch, lambda: R.rng_generate_fold(g, st, S, n, d, fold), 5)
+            rate = S * n / (ms * 1e-3)
+            ms_wb = _time(torch, lambda: R.rng_generate(g, st, S, N_BULK, d, out), 5)
+            rate_wb = S * N_BULK / (ms_wb * 1e-3)
+            row[dname] = {"without_writeback_GSamples_s": round(rate / 1e9, 1),
+                          "with_writeback_GSamples_s": round(rate_wb / 1e9, 1),
+                          "useful_Gops_without_writeback": round(rate * USEFUL_OPS[name] / 1e9, 1)}
+        if name in PAPER_NO_WRITEBACK:
+            row["paper_gtx280_without_writeback_GSamples_s"] = dict(zip(("u32", "f32"), PAPER_NO_WRITEBACK[name]))
+        res[name] = row
+    del out
+    torch.cuda.empty_cache()
+    return {"without_writeback_2^20x2^12": res}
 
 
 def placement_workload(torch, R, dev):

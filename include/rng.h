@@ -175,6 +175,16 @@ int rng_generate_leapfrog(int g, const uint32_t *d_state_one, uint64_t total, ui
 int rng_fused_pi(int g, uint32_t *d_state, uint64_t n_streams, uint64_t n,
                  uint64_t *d_count, void *stream);
 
+/* The "without write-back" mode of the paper's Tables I-III (Sec. III.B),
+ * for every generator: each stream draws n numbers (uint32, or their FP32
+ * bit patterns for t = RNG_F32) and d_fold[s] ([n_streams] uint32, device)
+ * is XORed with the XOR of stream s's n outputs; nothing else is stored and
+ * the states are written back.  Every number is computed, so the rate is the
+ * generator's arithmetic-bound one.  Clear d_fold first for the plain XOR.
+ * Few streams are cut into jumped chunks whose folds combine by atomic XOR. */
+int rng_generate_fold(int g, uint32_t *d_state, uint64_t n_streams, uint64_t n, int t,
+                      uint32_t *d_fold, void *stream);
+
 /* The paper's XorShift placement comparison (Sec. III.A.2, Table II): the
  * r = 8 XorShift (eq. (5)) with each thread's eight state words
  *   RNG_XS_LDS_INDEXED   in LDS, read and written through a runtime

@@ -57,6 +57,7 @@ _SIGS = {
     "rng_fused_pi": (_int, [_int, _vp, _u64, _u64, _vp, _vp]),
     "rng_calibrate_valu": (_int, [_int, ctypes.POINTER(ctypes.c_double), _vp]),
     "rng_xs256_placement": (_int, [_int, _vp, _u64, _u64, _int, _vp, _vp, _vp]),
+    "rng_generate_fold": (_int, [_int, _vp, _u64, _u64, _int, _vp, _vp]),
     "rng_leapfrog_workspace_bytes": (_int, [_int, _u64, _pu64]),
     "rng_generate_leapfrog": (_int, [_int, _vp, _u64, _u64, _int, _vp, _vp, _vp, _u64, _vp]),
 }
@@ -249,6 +250,11 @@ def rng_generate_leapfrog(g, d_state_one, total, n_threads, t, d_out, d_final_st
 def rng_fused_pi(g, d_state, n_streams, n, d_count, stream=None):
     return _check(_lib.rng_fused_pi(g, _ptr(d_state), n_streams, n, _ptr(d_count), _stream(stream)),
                   "rng_fused_pi")
+
+
+def rng_generate_fold(g, d_state, n_streams, n, t, d_fold, stream=None):
+    return _check(_lib.rng_generate_fold(g, _ptr(d_state), n_streams, n, t, _ptr(d_fold), _stream(stream)),
+                  "rng_generate_fold")
 
 
 def rng_xs256_placement(placement, d_state, n_streams, n, t, d_out=None, d_fold=None, stream=None):

@@ -228,3 +228,19 @@ def test_large_grid_parity(rng, torch, oracle, name, dt, S, N, shape):
     ref = oracle.generate(o, ref_st, N, t, threads=16)
     assert np.array_equal(out.view(np.uint32), ref.view(np.uint32))
     assert np.array_equal(_host(st), ref_st)
+
+
+@pytest.mark.parametrize("name", GENS)
+@pytest.mark.parametrize("dt", ["u32", "f32"])
+@pytest.mark.parametrize("S,N", [(1, 1), (1000, 77), (64, 4096), (3, 100000), (70000, 16)])
+def test_fold_parity(rng, torch, oracle, name, dt, S, N):
+    """Without write-back: the per-stream XOR of the n outputs (chunked with jumps
+    for few streams) and the final states equal the oracle's."""
+    g, o, t = rng.GENERATORS[name], oracle.GENERATORS[name], rng.DTYPES[dt]
+    st = _dev_state(torch, rng, g, 61, S)
+    fold = torch.zeros(S, dtype=torch.int32, device="cuda")
+    rng.rng_generate_fold(g, st, S, N, t, fold)
+    ref_st = oracle.seed(o, 61, S)
+    ref = oracle.generate(o, ref_st, N, t, threads=4).view(np.uint32)
+    assert np.array_equal(_host(fold), np.bitwise_xor.reduce(ref, axis=1))
+    assert np.array_equal(_host(st), ref_st)
