@@ -245,8 +245,8 @@ int rng_batch_create(uint32_t max_requests, uint64_t max_samples, rng_batch_t **
  * its table).  No two requests may share a stream state.  Blocks until the
  * previous launch's plan upload has left the staging buffers. */
 int rng_batch_set(rng_batch_t *h, const rng_request_t *h_reqs, uint32_t n);
-/* Queue the planned batch on stream: plan upload, then the graph (counter
- * reset, root jumps, tree levels, persistent generation). */
+/* Queue the planned batch on stream: plan upload, then the graph (root
+ * jumps, tree levels, persistent generation). */
 int rng_batch_launch(rng_batch_t *h, void *stream);
 /* Persistent-kernel shape: wg lanes per workgroup (64..512), unroll
  * (samples per generation step) and chunk length C (a multiple of 64);

@@ -1,8 +1,8 @@
 // rng_batch.cpp -- the batched path of the C ABI: plans a batch of
 // independent requests (chunking, grouping by generator and dtype, the
 // radix-16 tree work lists), ships the plan through pinned host memory, and
-// replays one captured HIP graph per batch shape: counter reset, root jumps,
-// tree levels, persistent generation kernel.
+// replays one captured HIP graph per batch shape: root jumps (which also
+// reset the tile counter), tree levels, persistent generation kernel.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -15,7 +15,6 @@
 #include "rng_batch_internal.hpp"
 
 namespace rngx {
-int launch_batch_reset(uint32_t *counter, hipStream_t s);
 int launch_batch_root(const BatchArgs &a, uint32_t max_requests, hipStream_t s);
 int launch_batch_level(const BatchArgs &a, uint32_t level, unsigned grid, hipStream_t s);
 int launch_batch_gen(const BatchArgs &a, int wg, int unroll, unsigned grid, hipStream_t s);
@@ -406,8 +405,7 @@ int rng_batch_launch(rng_batch_t *h, void *stream)
         hipStream_t cs = h->capture;
         if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return hip_fail(e, "hipStreamBeginCapture");
-        int rc = launch_batch_reset(h->d_counter, cs);
-        if (!rc) rc = launch_batch_root(a, h->max_requests, cs);
+        int rc = launch_batch_root(a, h->max_requests, cs);
         for (uint32_t l = 0; !rc && l < H.levels; ++l) rc = launch_batch_level(a, l, level_grid, cs);
         if (!rc) rc = launch_batch_gen(a, (int)h->wg, (int)h->unroll, gen_grid, cs);
         e = hipStreamEndCapture(cs, &g.graph);

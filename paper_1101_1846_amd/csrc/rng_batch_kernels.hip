@@ -36,13 +36,13 @@ __device__ __forceinline__ void with_gen(uint32_t g, F &&f)
     }
 }
 
-__global__ void k_batch_reset(uint32_t *counter) { counter[0] = 0; }
-
 // Root of each request's tree: its state jumped by `offset` becomes the start
-// of chunk 0 (or, for an empty request, is written straight back).
+// of chunk 0 (or, for an empty request, is written straight back).  Also
+// clears the generation kernel's tile counter.
 __global__ __launch_bounds__(256) void k_batch_root(BatchArgs a)
 {
     const BatchHeader &h = *a.hdr;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.counter[0] = 0;  // tile counter of the generation kernel
     for (uint32_t r = blockIdx.x * 256 + threadIdx.x; r < h.n; r += gridDim.x * 256) {
         const BatchReq q = a.reqs[r];
         const BatchGroup &gr = h.groups[q.group];
@@ -218,7 +218,10 @@ __device__ void batch_tile(const BatchArgs &a, const BatchGroup &gr, uint32_t ti
     if (active && j + 1 == q.nchunks) g.store(q.state, q.stride, 0);
 }
 
-// Persistent generation: every wavefront loops on an atomic tile counter.
+// Persistent generation.  Wave w of the grid's W waves takes tile w first;
+// the tiles from W on are pulled from an atomic counter (reset by the root
+// kernel), so a batch with fewer tiles than waves issues no atomics and the
+// waves without a tile leave at once.
 template <int WG, int U>
 __global__ __launch_bounds__(WG) void k_batch_gen(BatchArgs a)
 {
@@ -229,10 +232,9 @@ __global__ __launch_bounds__(WG) void k_batch_gen(BatchArgs a)
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const BatchHeader &h = *a.hdr;
-    for (;;) {
-        uint32_t t = 0;
-        if (lane == 0) t = atomicAdd(a.counter, 1u);
-        t = __builtin_amdgcn_readfirstlane(__shfl(t, 0, 64));
+    const uint32_t nwaves = gridDim.x * NW;
+    uint32_t t = blockIdx.x * NW + wv;
+    for (;; ) {
         if (t >= h.n_tiles) break;
         uint32_t gi = 0;
         while (gi + 1 < h.ngroups && t >= h.groups[gi].tile_end) ++gi;
@@ -250,16 +252,14 @@ __global__ __launch_bounds__(WG) void k_batch_gen(BatchArgs a)
             RNGX_BATCH_CASE(GenMWC1616, G_MWC1616)
 #undef RNGX_BATCH_CASE
         }
+        if (nwaves >= h.n_tiles) break;  // every tile was handed out statically
+        uint32_t next = 0;
+        if (lane == 0) next = atomicAdd(a.counter, 1u);
+        t = nwaves + __builtin_amdgcn_readfirstlane(__shfl(next, 0, 64));
     }
 }
 
 // ------------------------------------------------------------------ launchers
-int launch_batch_reset(uint32_t *counter, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, counter);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
-}
-
 int launch_batch_root(const BatchArgs &a, uint32_t max_requests, hipStream_t s)
 {
     unsigned grid = (max_requests + 255) / 256;
