@@ -99,7 +99,10 @@ int rng_seed(int g, uint64_t seed, uint64_t first_stream, uint64_t n_streams,
  * aligned (16-byte alignment with n % 4 == 0 takes 128-bit stores).
  * n = 0 or n_streams = 0 is a no-op.  When n_streams is small the library
  * splits each stream into chunks that start from jumped-ahead states, so the
- * output is still the serial sequence of every stream. */
+ * output is still the serial sequence of every stream.  The states are then
+ * written back only after every chunk has read them: inside the kernel when
+ * one workgroup holds all chunks of its streams, else by a second launch on
+ * the same stream that advances them by n. */
 int rng_generate(int g, uint32_t *d_state, uint64_t n_streams, uint64_t n, int t,
                  void *d_out, void *stream);
 
@@ -181,7 +184,8 @@ int rng_fused_pi(int g, uint32_t *d_state, uint64_t n_streams, uint64_t n,
  * is XORed with the XOR of stream s's n outputs; nothing else is stored and
  * the states are written back.  Every number is computed, so the rate is the
  * generator's arithmetic-bound one.  Clear d_fold first for the plain XOR.
- * Few streams are cut into jumped chunks whose folds combine by atomic XOR. */
+ * Few streams are cut into jumped chunks whose folds combine by atomic XOR;
+ * their states are then advanced by a second launch. */
 int rng_generate_fold(int g, uint32_t *d_state, uint64_t n_streams, uint64_t n, int t,
                       uint32_t *d_fold, void *stream);
 

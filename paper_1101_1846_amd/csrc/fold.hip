@@ -4,7 +4,8 @@
 // and the final state.  Every number is computed (the XOR keeps it live and
 // checkable), so the rate is the generator's VALU-bound rate.  Few streams
 // are cut into chunks whose starts come from jump-ahead (uniform per wave);
-// chunk folds combine by atomic XOR.
+// chunk folds combine by atomic XOR, and the states are then advanced by a
+// separate skip launch (no chunk may overwrite a start state others read).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(256) void k_fold(FoldArgs a)
     if (!valid) return;
     if (a.P == 1) a.fold[s] ^= acc;
     else atomicXor(&a.fold[s], acc);
-    if (ke == a.N) g.store(a.state, a.ld, s);
+    if (a.P == 1) g.store(a.state, a.ld, s);  // P > 1: the host skips the states by N
 }
 
 template <class G>
@@ -104,5 +105,7 @@ extern "C" int rng_generate_fold(int g, uint32_t *d_state, uint64_t n_streams, u
     case RNG_KISS: rc = launch_fold<GenKISS>(t, a, st); break;
     case RNG_MWC1616: rc = launch_fold<GenMWC1616>(t, a, st); break;
     }
-    return check_launch(rc, "rng_generate_fold");
+    if (int e = check_launch(rc, "rng_generate_fold")) return e;
+    if (a.P == 1) return RNG_OK;
+    return check_launch(dispatch_skip(g, d_state, n_streams, n_streams, n, tab, st), "rng_generate_fold: state");
 }

@@ -209,9 +209,9 @@ int dispatch_seed(int g, uint64_t seed, uint64_t first, uint64_t S, uint32_t *st
     RNGX_GEN_SWITCH(g, launch_seed_t<G>(seed, first, S, st, tab, s))
 }
 
-int dispatch_skip(int g, uint32_t *st, uint64_t S, uint64_t k, const DevTables &tab, hipStream_t s)
+int dispatch_skip(int g, uint32_t *st, uint64_t ld, uint64_t S, uint64_t k, const DevTables &tab, hipStream_t s)
 {
-    RNGX_GEN_SWITCH(g, launch_skip_t<G>(st, S, k, tab, s))
+    RNGX_GEN_SWITCH(g, launch_skip_t<G>(st, ld, S, k, tab, s))
 }
 
 int dispatch_tree_level(int g, uint32_t *ws, uint64_t T, uint32_t shift, uint64_t unit, const DevTables &tab,
@@ -263,8 +263,11 @@ int generate_impl(int g, int dt, uint32_t *d_state, uint64_t ld, uint64_t S, uin
     a.nt = 0;  // plain stores: the streaming hint measured slower for these writes
     a.tab = tab;
     choose_chunks(g, S, N, kGenTile, &a.C, &a.P);
-    return check_launch(dispatch_generate(g, dt, a, (int)shape.wg, (int)shape.unroll, staged, st),
-                        "rng_generate");
+    rc = dispatch_generate(g, dt, a, (int)shape.wg, (int)shape.unroll, staged, st);
+    if (rc != kStatesNotWritten) return check_launch(rc, "rng_generate");
+    // chunks of one stream in several workgroups: the states advance after
+    // every chunk has read them
+    return check_launch(dispatch_skip(g, d_state, ld, S, N, tab, st), "rng_generate: state");
 }
 
 int check_gen(int g) { return gen_words(g) ? RNG_OK : fail(RNG_EINVAL, "unknown generator %d", g); }
@@ -389,7 +392,7 @@ int rng_skip(int g, uint32_t *d_state, uint64_t n_streams, uint64_t k, void *str
     if (int rc = check_sizes(n_streams, 1, gen_words(g))) return rc;
     DevTables tab;
     if (int rc = device_tables(&tab)) return rc;
-    return check_launch(dispatch_skip(g, d_state, n_streams, k, tab, (hipStream_t)stream), "rng_skip");
+    return check_launch(dispatch_skip(g, d_state, n_streams, n_streams, k, tab, (hipStream_t)stream), "rng_skip");
 }
 
 int rng_split_workspace_bytes(int g, uint64_t n_threads, uint64_t *bytes)
@@ -476,7 +479,10 @@ int rng_fused_pi(int g, uint32_t *d_state, uint64_t n_streams, uint64_t n, uint6
     a.tab = tab;
     choose_chunks(g, n_streams, n, 8, &a.C, &a.P);
     if (a.P == 1) a.C = n;
-    return check_launch(dispatch_fused(g, a, (hipStream_t)stream), "rng_fused_pi");
+    if (int rc = check_launch(dispatch_fused(g, a, (hipStream_t)stream), "rng_fused_pi")) return rc;
+    if (a.P == 1) return RNG_OK;
+    return check_launch(dispatch_skip(g, d_state, n_streams, n_streams, n, tab, (hipStream_t)stream),
+                        "rng_fused_pi: state");
 }
 
 }  // extern "C"

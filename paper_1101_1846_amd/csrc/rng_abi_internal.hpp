@@ -25,7 +25,7 @@ void choose_chunks(int g, uint64_t S, uint64_t N, uint64_t align, uint64_t *C, u
 int generate_impl(int g, int dt, uint32_t *d_state, uint64_t ld, uint64_t S, uint64_t N, void *d_out,
                   Shape shape, bool staged, hipStream_t st);
 int dispatch_generate(int g, int dt, const GenArgs &a, int wg, int unroll, bool staged, hipStream_t st);
-int dispatch_skip(int g, uint32_t *st, uint64_t S, uint64_t k, const DevTables &tab, hipStream_t s);
+int dispatch_skip(int g, uint32_t *st, uint64_t ld, uint64_t S, uint64_t k, const DevTables &tab, hipStream_t s);
 // One radix-16 level of a thread-start tree: threads [2^shift, min(2^(shift+4), T))
 // of ws ([W][T]) from the threads below 2^shift, unit samples per thread index.
 int dispatch_tree_level(int g, uint32_t *ws, uint64_t T, uint32_t shift, uint64_t unit, const DevTables &tab,

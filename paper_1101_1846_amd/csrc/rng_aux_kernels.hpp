@@ -30,15 +30,15 @@ __global__ __launch_bounds__(256) void k_seed(uint32_t *__restrict__ st, uint64_
 
 // ------------------------------------------------------------------ skip
 template <class G>
-__global__ __launch_bounds__(256) void k_skip(uint32_t *__restrict__ st, uint64_t S, uint64_t k,
+__global__ __launch_bounds__(256) void k_skip(uint32_t *__restrict__ st, uint64_t ld, uint64_t S, uint64_t k,
                                               DevTables tab)
 {
     uint64_t s = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     if (s >= S) return;
     G g;
-    g.load(st, S, s, tab);
+    g.load(st, ld, s, tab);
     g.jump(k, tab);
-    g.store(st, S, s);
+    g.store(st, ld, s);
 }
 
 // One level of the radix-16 tree that starts the threads of a split
@@ -114,9 +114,9 @@ int launch_seed_t(uint64_t seed, uint64_t first, uint64_t S, uint32_t *st, const
 }
 
 template <class G>
-int launch_skip_t(uint32_t *st, uint64_t S, uint64_t k, const DevTables &tab, hipStream_t stream)
+int launch_skip_t(uint32_t *st, uint64_t ld, uint64_t S, uint64_t k, const DevTables &tab, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_skip<G>, dim3(grid_for(S, 256)), dim3(256), 0, stream, st, S, k, tab);
+    hipLaunchKernelGGL(k_skip<G>, dim3(grid_for(S, 256)), dim3(256), 0, stream, st, ld, S, k, tab);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

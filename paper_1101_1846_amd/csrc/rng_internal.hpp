@@ -26,6 +26,15 @@ constexpr int gen_tile_depth(int wg) { return wg * (kGenTile + 4) * 4 <= 160 * 1
 #endif
 constexpr int kStoreMode = RNGX_STORE_MODE;
 
+// Chunked launches (P > 1 chunks per stream) whose workgroups each hold every
+// chunk of their 64-stream groups: the kernel orders the start-state reads
+// before the write-back with a barrier.
+__host__ __device__ constexpr bool chunks_in_workgroup(uint32_t P, int nw) { return P > 1 && nw % P == 0; }
+
+// Launcher result: launched, but the states were not written back (the
+// caller advances them by N with a skip launch).
+constexpr int kStatesNotWritten = 1;
+
 // Resident schedule for one-chunk launches of whole stream groups: a wave
 // preloads the states of all its groups before its first store.  The register
 // queue holds up to this many groups: enough for 2^20 streams on the waves the
@@ -60,7 +69,7 @@ template <class G>
 int launch_seed_t(uint64_t seed, uint64_t first, uint64_t S, uint32_t *st, const DevTables &tab,
                   hipStream_t stream);
 template <class G>
-int launch_skip_t(uint32_t *st, uint64_t S, uint64_t k, const DevTables &tab, hipStream_t stream);
+int launch_skip_t(uint32_t *st, uint64_t ld, uint64_t S, uint64_t k, const DevTables &tab, hipStream_t stream);
 template <class G>
 int launch_tree_level_t(uint32_t *ws, uint64_t T, uint32_t shift, uint64_t unit, const DevTables &tab,
                         hipStream_t stream);

@@ -90,8 +90,12 @@ __device__ __forceinline__ void store_tile(const uint32_t *tile, uint32_t *out, 
 // Lane mapping: wave w serves streams [64 sb, 64 sb + 64) for chunk j, with
 // sb = w / P and j = w % P.  Chunk j covers samples [j C, min((j+1) C, N)) of
 // each of its streams and starts from the stream state jumped by j C (the
-// jump distance is uniform across the wave).  The last chunk writes the
-// state back.
+// jump distance is uniform across the wave).  With one chunk per stream the
+// kernel writes the state back.  With several, the last chunk may write it
+// only once every chunk has read the start state: when one workgroup holds
+// all of a group's chunks a barrier orders that; otherwise nothing does, the
+// launcher reports it, and the host advances the states by N in a separate
+// launch after this one.
 //
 // Store paths.  kMode 0: every lane stores its own row straight from
 // registers.  kMode 1 and 2 stage through a wave-private LDS tile
@@ -205,9 +209,14 @@ __global__ __launch_bounds__(WG) void k_generate(GenArgs a)
     }
     const uint64_t sb = wave / a.P, j = wave - sb * a.P;
     const uint64_t s0 = sb * 64;
-    if (s0 >= a.S) return;
     const uint64_t kb = j * a.C;
-    if (kb >= a.N) return;
+    // When the workgroup holds every chunk of its groups, a barrier after all
+    // of them have read their start states lets the last chunk write back.
+    const bool sync_wb = chunks_in_workgroup(a.P, NW);
+    if (s0 >= a.S || kb >= a.N) {  // uniform per wave
+        if (sync_wb) __syncthreads();
+        return;
+    }
     const uint64_t ke = min(kb + a.C, a.N);
     const uint32_t rows = (uint32_t)min<uint64_t>(64, a.S - s0);
     const bool valid = (uint32_t)lane < rows;
@@ -215,6 +224,10 @@ __global__ __launch_bounds__(WG) void k_generate(GenArgs a)
 
     G g;
     g.load(a.state, a.ld, s, a.tab);
+    if (sync_wb) {
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's start state has arrived
+        __syncthreads();
+    }
     if (j) g.jump(kb, a.tab);
 
     uint32_t *tile = kStaged ? &lds[wv * 64 * LD] : nullptr;
@@ -303,7 +316,7 @@ __global__ __launch_bounds__(WG) void k_generate(GenArgs a)
             }
         }
     }
-    if (valid && ke == a.N) g.store(a.state, a.ld, s);
+    if (valid && ke == a.N && (a.P == 1 || sync_wb)) g.store(a.state, a.ld, s);
 }
 
 // ------------------------------------------------------------------ fused pi
@@ -361,7 +374,7 @@ __global__ __launch_bounds__(WG) void k_fused_pi(FusedArgs a)
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) total += __shfl_xor(total, off, 64);
     if (lane == 0 && total) atomicAdd((unsigned long long *)a.count, (unsigned long long)total);
-    if (valid && ke == a.N) g.store(a.state, a.ld, s);
+    if (valid && a.P == 1) g.store(a.state, a.ld, s);  // P > 1: the host skips the states by N
 }
 
 // ------------------------------------------------------------------ launchers
@@ -396,7 +409,8 @@ int launch_generate_shape(const GenArgs &a, hipStream_t stream)
         }
     }
     hipLaunchKernelGGL((k_generate<G, DT, WG, U, K, kMode>), dim3((unsigned)blocks), dim3(WG), 0, stream, b);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
+    if (hipGetLastError() != hipSuccess) return -1;
+    return a.P > 1 && !chunks_in_workgroup(a.P, WG / 64) ? kStatesNotWritten : 0;
 }
 
 template <class G, int DT, int WG>
@@ -446,7 +460,8 @@ int launch_fused_pi_t(const FusedArgs &a, hipStream_t stream)
 #define RNGX_INSTANTIATE(G)                                                                            \
     template int launch_seed_t<G>(uint64_t, uint64_t, uint64_t, uint32_t *, const DevTables &,        \
                                   hipStream_t);                                                        \
-    template int launch_skip_t<G>(uint32_t *, uint64_t, uint64_t, const DevTables &, hipStream_t);    \
+    template int launch_skip_t<G>(uint32_t *, uint64_t, uint64_t, uint64_t, const DevTables &,        \
+                                  hipStream_t);                                                        \
     template int launch_tree_level_t<G>(uint32_t *, uint64_t, uint32_t, uint64_t, const DevTables &,  \
                                         hipStream_t);                                                  \
     template int launch_state_copy_t<G>(const uint32_t *, uint64_t, uint64_t, uint32_t *, uint64_t,  \

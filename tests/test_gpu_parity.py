@@ -118,6 +118,25 @@ def test_resume_equals_one_call(rng, torch, oracle, name):
 
 
 @pytest.mark.parametrize("name", GENS)
+@pytest.mark.parametrize("shape", [(64, 4), (256, 4), (1024, 4)])
+def test_chunked_resume_equals_one_call(rng, torch, oracle, name, shape):
+    """Few streams with long rows are cut into chunks that each start from the
+    stream's state by jump-ahead; the states must come back advanced by exactly
+    N, written only after every chunk has read them.  With 1024-lane
+    workgroups each workgroup holds all chunks of its streams (2-16 of them)
+    and the kernel writes the states back after a barrier; with 64 lanes a
+    separate skip launch advances them.  Three calls in a row, then the oracle."""
+    g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
+    S, N = 64, 32768 if name == "XS256" else 2048
+    a = _dev_state(torch, rng, g, 12, S)
+    parts = [_gen(torch, rng, g, a, S, N, rng.RNG_U32, shape=shape) for _ in range(3)]
+    ref_st = oracle.seed(o, 12, S)
+    ref = oracle.generate(o, ref_st, 3 * N, threads=4)
+    assert np.array_equal(np.concatenate(parts, axis=1), ref)
+    assert np.array_equal(_host(a), ref_st)
+
+
+@pytest.mark.parametrize("name", GENS)
 def test_run_twice_identical(rng, torch, name):
     g = rng.GENERATORS[name]
     S, N = 4096, 512
