@@ -246,8 +246,9 @@ typedef struct rng_batch rng_batch_t;
  * pinned staging buffers, and its graphs.  Created on the current device. */
 int rng_batch_create(uint32_t max_requests, uint64_t max_samples, rng_batch_t **h);
 /* Plan a batch from a host table of n requests (copied; the caller may reuse
- * its table).  No two requests may share a stream state.  Blocks until the
- * previous launch's plan upload has left the staging buffers. */
+ * its table).  No two requests may share a stream state (the same d_state
+ * twice is RNG_EINVAL; overlapping strided states are not detected).  Blocks
+ * until the previous launch's plan upload has left the staging buffers. */
 int rng_batch_set(rng_batch_t *h, const rng_request_t *h_reqs, uint32_t n);
 /* Queue the planned batch on stream: plan upload, then the graph (root
  * jumps, tree levels, persistent generation). */

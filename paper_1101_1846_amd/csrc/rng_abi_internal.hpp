@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "rng.h"
 #include "rng_internal.hpp"
 
 namespace rngx {
@@ -33,4 +34,7 @@ int dispatch_tree_level(int g, uint32_t *ws, uint64_t T, uint32_t shift, uint64_
 int dispatch_state_copy(int g, const uint32_t *src, uint64_t ss, uint64_t si, uint32_t *dst, uint64_t ds,
                         uint64_t di, hipStream_t s);
 
+// rng_batch_set without the check that no two requests share a state (for
+// callers that keep one request per state).
+int batch_set_distinct(rng_batch_t *h, const rng_request_t *reqs, uint32_t n);
 }  // namespace rngx

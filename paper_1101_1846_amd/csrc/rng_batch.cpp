@@ -240,11 +240,33 @@ int rng_batch_set(rng_batch_t *h, const rng_request_t *reqs, uint32_t n)
 {
     if (!h) return fail(RNG_EINVAL, "NULL handle");
     if (n && !reqs) return fail(RNG_EINVAL, "NULL request table");
+    if (n > h->max_requests) return fail(RNG_ENOMEM, "%u requests > capacity %u", n, h->max_requests);
+    if (n > 1) {
+        // two requests on one state would race on its write-back
+        std::vector<uintptr_t> p(n);
+        for (uint32_t i = 0; i < n; ++i) p[i] = (uintptr_t)reqs[i].d_state;
+        std::sort(p.begin(), p.end());
+        if (std::adjacent_find(p.begin(), p.end()) != p.end())
+            return fail(RNG_EINVAL, "two requests share one d_state");
+    }
+    return batch_set_distinct(h, reqs, n);
+}
+
+}  // extern "C"
+
+// rng_batch_set for callers that already keep one request per state (the
+// server's batches).
+int rngx::batch_set_distinct(rng_batch_t *h, const rng_request_t *reqs, uint32_t n)
+{
+    if (!h) return fail(RNG_EINVAL, "NULL handle");
+    if (n && !reqs) return fail(RNG_EINVAL, "NULL request table");
     std::lock_guard<std::mutex> lk(h->mu);
     int rc = plan(h, reqs, n);
     if (rc == RNG_OK) h->last.assign(reqs, reqs + n);
     return rc;
 }
+
+extern "C" {
 
 static int plan(rng_batch_t *h, const rng_request_t *reqs, uint32_t n)
 {

@@ -206,7 +206,7 @@ static void worker_loop(rng_server *h)
                 }
             }
             if (!chosen.empty()) {
-                int rc = rng_batch_set(free_slot->batch, table.data(), (uint32_t)table.size());
+                int rc = batch_set_distinct(free_slot->batch, table.data(), (uint32_t)table.size());
                 if (!rc) rc = rng_batch_launch(free_slot->batch, free_slot->stream);
                 if (!rc && hipEventRecord(free_slot->ev, free_slot->stream) != hipSuccess) rc = RNG_EHIP;
                 if (rc) {

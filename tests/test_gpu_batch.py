@@ -225,6 +225,12 @@ def test_batch_validation(rng, torch):
         for b in bad:
             arr = rng.make_requests(b)
             assert L.rng_batch_set(h, arr, 1) == rng.RNG_EINVAL
+        shared = rng.make_requests([(rng.RNG_XS32, 0, st, 1, 0, 10, out),
+                                    (rng.RNG_XS32, 0, st, 1, 5, 10, out.data_ptr() + 64)])
+        assert L.rng_batch_set(h, shared, 2) == rng.RNG_EINVAL  # one state, two requests
+        distinct = rng.make_requests([(rng.RNG_XS32, 0, st, 1, 0, 10, out),
+                                      (rng.RNG_XS32, 0, st.data_ptr() + 4, 1, 5, 10, out.data_ptr() + 64)])
+        assert L.rng_batch_set(h, distinct, 2) == rng.RNG_OK
         too_many = rng.make_requests([(rng.RNG_XS32, 0, st, 1, 0, 1, out)] * 5)
         assert L.rng_batch_set(h, too_many, 5) == rng.RNG_ENOMEM
         too_long = rng.make_requests([(rng.RNG_XS32, 0, st, 1, 0, 1001, out)])
