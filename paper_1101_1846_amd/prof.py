@@ -77,6 +77,8 @@ def pmc_record(fetch_db, write_db, key):
 
 
 def main(argv):
+    if not argv:
+        raise SystemExit(__doc__)
     if argv[0] == "trace":
         table, _ = trace_table(argv[1])
         print(table)
