@@ -322,10 +322,29 @@ def split_workload(torch, R, dev):
         wsb = R.rng_split_workspace_bytes(g, T)
         ws = torch.empty(wsb // 4, dtype=torch.int32, device=dev)
         ms = _time(torch, lambda: R.rng_generate_split(g, s1, total, T, R.RNG_U32, o, fin, ws, wsb), 5)
+        # the generation phase alone: the same launch over T states of T x (total / T) samples
+        st = torch.empty((W, T), dtype=torch.int32, device=dev)
+        R.rng_seed(g, 2, 0, T, st)
+        gen_ms = _time(torch, lambda: R.rng_generate(g, st, T, total // T, R.RNG_U32, o), 5)
         res["split_2^30_%s" % name] = {"ms": round(ms, 3),
                                        "GSamples_s": round(total / (ms * 1e-3) / 1e9, 1),
-                                       "GB_s": round(4 * total / (ms * 1e-3) / 1e9, 1)}
-        del ws
+                                       "GB_s": round(4 * total / (ms * 1e-3) / 1e9, 1),
+                                       "generation_ms": round(gen_ms, 3),
+                                       "setup_ms": round(max(ms - gen_ms, 0.0), 3)}
+        del ws, st
+    # jump-ahead alone: every one of 2^20 states skipped by one 64-bit distance
+    # (38 set bits: 38 modular or GF(2) products per state)
+    K = 0x9E3779B97F4A7C15
+    for name in ("MWC32", "MWC1616", "XS32", "KISS", "XS256"):
+        g = R.GENERATORS[name]
+        W = R.rng_state_words(g)
+        st = torch.empty((W, T), dtype=torch.int32, device=dev)
+        R.rng_seed(g, 2, 0, T, st)
+        ms = _time(torch, lambda: R.rng_skip(g, st, T, K), 5)
+        res["skip_2^20_states_%s" % name] = {"us": round(ms * 1e3, 1),
+                                             "Gjumps_s": round(T / (ms * 1e-3) / 1e9, 2),
+                                             "state_GB_s": round(2 * 4 * W * T / (ms * 1e-3) / 1e9, 1)}
+        del st
     # the same sequence by leapfrogging: thread j emits numbers j, j + T, ...
     for name in ("MWC32", "XS32", "KISS", "MWC1616", "XS256"):
         g = R.GENERATORS[name]

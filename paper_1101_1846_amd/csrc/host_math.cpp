@@ -248,17 +248,27 @@ uint64_t mwc32_fold_const(uint64_t k)
     return mulmod64(powmod64(T.mwc32_a, k, m), two64, m);
 }
 
-Gf2Mat<8> xs256_pow(uint64_t k)
+void xs32_lcg_jump(uint64_t k, uint32_t cols[32], uint32_t *lcg_a, uint32_t *lcg_c)
 {
     const HostTables &T = host_tables();
-    Gf2Mat<8> r = Gf2Mat<8>::identity();
+    uint32_t A = 1, C = 0;  // identity affine map
+    for (int i = 0; i < 32; ++i) cols[i] = 1u << i;
     for (int b = 0; b < kPowBits; ++b) {
         if (!((k >> b) & 1)) continue;
-        Gf2Mat<8> p;
-        std::memcpy(p.c, &T.xs256_pow[(size_t)b * 2048], sizeof(p.c));
-        r = p * r;
+        const uint32_t pa = T.lcg_pow[b][0], pc = T.lcg_pow[b][1];
+        C = pa * C + pc;  // 2^b more steps after the current map
+        A = pa * A;
+        // column i <- M^(2^b) column i, branch-free with the columns innermost
+        // (data-dependent branches here cost more than the arithmetic)
+        uint32_t next[32] = {0};
+        for (int j = 0; j < 32; ++j) {
+            const uint32_t pj = T.xs32_pow[b][j];
+            for (int i = 0; i < 32; ++i) next[i] ^= pj & (0u - ((cols[i] >> j) & 1u));
+        }
+        for (int i = 0; i < 32; ++i) cols[i] = next[i];
     }
-    return r;
+    *lcg_a = A;
+    *lcg_c = C;
 }
 
 }  // namespace rngx

@@ -58,9 +58,10 @@ struct HostTables {
 void xs256_nibble_table(const uint32_t *cols, uint32_t *t4);
 const HostTables &host_tables();
 
-// Fold-domain constants for an arbitrary jump distance (used by the host for
-// chunked launches; the device composes powers of two itself).
+// Constants of a k-step map, composed from the power tables on the host (for
+// the kernels that move many states, or many threads, by one distance).
 uint64_t mwc32_fold_const(uint64_t k);
-Gf2Mat<8> xs256_pow(uint64_t k);
+// Columns of M^k for xorshift32 (eq. (6)) and the (A_k, C_k) of k LCG steps.
+void xs32_lcg_jump(uint64_t k, uint32_t cols[32], uint32_t *lcg_a, uint32_t *lcg_c);
 
 }  // namespace rngx

@@ -185,22 +185,8 @@ int launch_leapfrog(int dt, const LeapArgs &a, hipStream_t s)
 // Host-side T-step constants from the power tables.
 void host_leap_constants(uint64_t T, LeapArgs &a)
 {
-    const HostTables &H = host_tables();
     a.mwc32_af = mwc32_fold_const(T);
-    uint32_t A = 1, C = 0;  // identity affine map
-    Gf2Mat<1> M = Gf2Mat<1>::identity();
-    for (int b = 0; b < kPowBits; ++b) {
-        if (!((T >> b) & 1)) continue;
-        const uint32_t pa = H.lcg_pow[b][0], pc = H.lcg_pow[b][1];
-        C = pa * C + pc;  // apply 2^b steps after the current map
-        A = pa * A;
-        Gf2Mat<1> P;
-        for (int i = 0; i < 32; ++i) P.c[i][0] = H.xs32_pow[b][i];
-        M = P * M;
-    }
-    a.lcg_a = A;
-    a.lcg_c = C;
-    for (int i = 0; i < 32; ++i) a.xs32[i] = M.c[i][0];
+    xs32_lcg_jump(T, a.xs32, &a.lcg_a, &a.lcg_c);
 }
 
 }  // namespace

@@ -209,11 +209,6 @@ int dispatch_seed(int g, uint64_t seed, uint64_t first, uint64_t S, uint32_t *st
     RNGX_GEN_SWITCH(g, launch_seed_t<G>(seed, first, S, st, tab, s))
 }
 
-int dispatch_skip(int g, uint32_t *st, uint64_t ld, uint64_t S, uint64_t k, const DevTables &tab, hipStream_t s)
-{
-    RNGX_GEN_SWITCH(g, launch_skip_t<G>(st, ld, S, k, tab, s))
-}
-
 int dispatch_tree_level(int g, uint32_t *ws, uint64_t T, uint32_t shift, uint64_t unit, const DevTables &tab,
                         hipStream_t s)
 {

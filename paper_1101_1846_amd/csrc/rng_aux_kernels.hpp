@@ -1,5 +1,5 @@
-// rng_aux_kernels.hpp -- the kernels around generation: seeding, skipping,
-// the radix-16 thread-start tree of split and leapfrogged sequences, and a
+// rng_aux_kernels.hpp -- the kernels around generation: seeding, the
+// radix-16 thread-start tree of split and leapfrogged sequences, and a
 // state copy, with their launchers (instantiated per generator together with
 // the generation kernels of rng_kernels.hpp).
 #pragma once
@@ -26,19 +26,6 @@ __global__ __launch_bounds__(256) void k_seed(uint32_t *__restrict__ st, uint64_
     G g;
     g.seed(d, tab);
     g.store(st, S, s);
-}
-
-// ------------------------------------------------------------------ skip
-template <class G>
-__global__ __launch_bounds__(256) void k_skip(uint32_t *__restrict__ st, uint64_t ld, uint64_t S, uint64_t k,
-                                              DevTables tab)
-{
-    uint64_t s = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (s >= S) return;
-    G g;
-    g.load(st, ld, s, tab);
-    g.jump(k, tab);
-    g.store(st, ld, s);
 }
 
 // One level of the radix-16 tree that starts the threads of a split
@@ -110,13 +97,6 @@ int launch_seed_t(uint64_t seed, uint64_t first, uint64_t S, uint32_t *st, const
                   hipStream_t stream)
 {
     hipLaunchKernelGGL(k_seed<G>, dim3(grid_for(S, 256)), dim3(256), 0, stream, st, S, seed, first, tab);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
-}
-
-template <class G>
-int launch_skip_t(uint32_t *st, uint64_t ld, uint64_t S, uint64_t k, const DevTables &tab, hipStream_t stream)
-{
-    hipLaunchKernelGGL(k_skip<G>, dim3(grid_for(S, 256)), dim3(256), 0, stream, st, ld, S, k, tab);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -69,8 +69,6 @@ template <class G>
 int launch_seed_t(uint64_t seed, uint64_t first, uint64_t S, uint32_t *st, const DevTables &tab,
                   hipStream_t stream);
 template <class G>
-int launch_skip_t(uint32_t *st, uint64_t ld, uint64_t S, uint64_t k, const DevTables &tab, hipStream_t stream);
-template <class G>
 int launch_tree_level_t(uint32_t *ws, uint64_t T, uint32_t shift, uint64_t unit, const DevTables &tab,
                         hipStream_t stream);
 template <class G>

@@ -460,8 +460,6 @@ int launch_fused_pi_t(const FusedArgs &a, hipStream_t stream)
 #define RNGX_INSTANTIATE(G)                                                                            \
     template int launch_seed_t<G>(uint64_t, uint64_t, uint64_t, uint32_t *, const DevTables &,        \
                                   hipStream_t);                                                        \
-    template int launch_skip_t<G>(uint32_t *, uint64_t, uint64_t, uint64_t, const DevTables &,        \
-                                  hipStream_t);                                                        \
     template int launch_tree_level_t<G>(uint32_t *, uint64_t, uint32_t, uint64_t, const DevTables &,  \
                                         hipStream_t);                                                  \
     template int launch_state_copy_t<G>(const uint32_t *, uint64_t, uint64_t, uint32_t *, uint64_t,  \

@@ -159,6 +159,27 @@ def test_skip_parity(rng, torch, oracle, name, k):
 
 
 @pytest.mark.parametrize("name", GENS)
+@pytest.mark.parametrize("k", [3, 1 << 40, (1 << 64) - 1 - 12345])
+def test_skip_many_states(rng, torch, oracle, name, k):
+    """More states than one pass of the grid covers, so each workgroup strides
+    over several after building its k-step tables once.  Sampled states
+    (the first, the last, both sides of every stride boundary, and random
+    ones) against the oracle."""
+    g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
+    S = (1 << 20) + 4099
+    st = _dev_state(torch, rng, g, 21, S)
+    rng.rng_skip(g, st, S, k)
+    got = _host(st)
+    edges = [0, 1, 255, 256, S - 1]
+    for b in (65536, 131072, 1 << 20):
+        edges += [b - 1, b, b + 1]
+    idx = sorted(set(edges) | set(int(i) for i in np.random.default_rng(5).integers(0, S, 100)))
+    ref = np.concatenate([oracle.seed(o, 21, 1, first_stream=i) for i in idx], axis=1)
+    ref = oracle.skip(o, ref, k)
+    assert np.array_equal(got[:, idx], ref)
+
+
+@pytest.mark.parametrize("name", GENS)
 @pytest.mark.parametrize("total,threads", [(1, 1), (1000, 1), (1000, 7), (4096 * 7 + 3, 64), (100000, 1000),
                                           (65536, 65536), (5, 8)])
 def test_split_parity(rng, torch, oracle, name, total, threads):
