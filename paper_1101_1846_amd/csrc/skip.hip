@@ -63,7 +63,7 @@ __global__ __launch_bounds__(kSkipWG) void k_skip_by(SkipArgs a)
     __shared__ uint16_t s_t392[kMwc16 ? kMwc16Count : 1];
     __shared__ uint32_t s_c16[kMwc16 ? kMwc16Count : 1];  // a_i^k * 2^48 mod m_i
     __shared__ uint32_t s_t8[kXs32 ? 1024 : 1];           // byte tables of the xorshift32 M^k
-    __shared__ uint4 s_t4[kXs256 ? 2048 : 1];              // staged M^(2^b), then the table of M^k
+    __shared__ uint4 s_t4[kXs256 ? 2 * 2048 : 1];          // staged M^(2^b) (two buffers), then M^k
     __shared__ uint32_t s_col[kXs256 ? 256 * 8 : 1];       // columns of M^k
     const uint32_t tid = threadIdx.x;
     if constexpr (kMwc16) {
@@ -91,12 +91,30 @@ __global__ __launch_bounds__(kSkipWG) void k_skip_by(SkipArgs a)
         uint32_t col[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) col[i] = (uint32_t)(tid / 32 == (uint32_t)i) << (tid % 32);
-        for (int b = 0; b < 64 && (a.k >> b); ++b) {  // uniform: k is the same for every thread
-            if (!((a.k >> b) & 1)) continue;
-            __syncthreads();  // the previous table is no longer read
-            stage_t4(s_t4, a.tab.xs256_t4 + (size_t)b * 2048);
+        // Set bits of k in increasing order (uniform: k is the same for every
+        // thread).  The table of the next one is loaded into registers while
+        // the current one is applied; buffer b & 1 is rewritten only after the
+        // barrier that follows the previous write, which every thread reaches
+        // after applying what that buffer held before.
+        constexpr int Q = 2048 / kSkipWG;
+        uint4 pre[Q];
+        uint64_t rest = a.k;  // non-zero: the host returns before launching for k = 0
+        int b = __builtin_ctzll(rest);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) pre[i] = a.tab.xs256_t4[(size_t)b * 2048 + tid + i * kSkipWG];
+        for (uint32_t buf = 0;; buf ^= 1) {
+            uint4 *t = s_t4 + buf * 2048;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) t[tid + i * kSkipWG] = pre[i];
             __syncthreads();
-            gf2_apply256_t4(s_t4, col);
+            rest &= rest - 1;
+            if (rest) {
+                b = __builtin_ctzll(rest);
+#pragma unroll
+                for (int i = 0; i < Q; ++i) pre[i] = a.tab.xs256_t4[(size_t)b * 2048 + tid + i * kSkipWG];
+            }
+            gf2_apply256_t4(t, col);
+            if (!rest) break;
         }
 #pragma unroll
         for (int i = 0; i < 8; ++i) s_col[tid * 8 + i] = col[i];
