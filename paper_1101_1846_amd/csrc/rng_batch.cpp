@@ -32,10 +32,8 @@ struct rng_batch {
     bool chunk_auto = false;  // C chosen per plan (RNG_BATCH_CHUNK_AUTO)
     uint32_t wg = 256, unroll = 8;
     uint64_t ws_words = 0;
-    BatchHeader *d_hdr = nullptr, *h_hdr = nullptr;
-    BatchReq *d_reqs = nullptr, *h_reqs = nullptr;
-    uint32_t *d_lvl = nullptr, *h_lvl = nullptr;  // [2 * seg_cap] segments, then block starts
-    uint64_t lvl_words = 0;
+    char *d_plan = nullptr, *h_plan = nullptr;  // packed plan (BatchHeader first), device and pinned staging
+    uint64_t plan_cap = 0;                      // bytes of each
     uint32_t *d_ws = nullptr, *d_counter = nullptr, *d_map = nullptr;
     hipEvent_t copied = nullptr;
     hipStream_t capture = nullptr;  // private stream the graphs are recorded on
@@ -49,7 +47,7 @@ struct rng_batch {
     std::vector<Graph> graphs;
     int num_cu = 256;
     std::vector<rng_request_t> last;  // last planned table, re-planned on a chunk change
-    uint32_t n_seg = 0, n_blk = 0;    // level segments and block starts of the current plan
+    BatchHeader &hdr() { return *(BatchHeader *)h_plan; }
 };
 
 // Automatic chunk length: a power of two in [min, 4096] that cuts the batch
@@ -74,9 +72,18 @@ static uint64_t seg_capacity(const rng_batch *h) { return (uint64_t)kBatchMaxLev
 
 // Block starts of all levels: the levels' work items sum to fewer than the
 // chunks, so sum(ceil(items / kLevelWG)) <= chunks / kLevelWG + levels.
-static uint64_t lvl_capacity(const rng_batch *h, uint64_t C)
+static uint64_t blk_capacity(const rng_batch *h, uint64_t C)
 {
-    return 2 * seg_capacity(h) + chunk_capacity(h, C) / kLevelWG + kBatchMaxLevels + 1;
+    return chunk_capacity(h, C) / kLevelWG + kBatchMaxLevels + 1;
+}
+
+static uint64_t align16(uint64_t x) { return (x + 15) & ~(uint64_t)15; }
+
+// Packed plan: header, requests, segments, block starts (16-byte aligned each).
+static uint64_t plan_capacity(const rng_batch *h, uint64_t C)
+{
+    return align16(sizeof(BatchHeader)) + align16(sizeof(BatchReq) * (uint64_t)h->max_requests) +
+           align16(8 * seg_capacity(h)) + 4 * blk_capacity(h, C);
 }
 
 // Sizes the chunk workspace, the chunk-to-request map and the level work
@@ -86,8 +93,9 @@ static int alloc_ws(rng_batch *h, uint64_t C)
 {
     const uint64_t chunks = chunk_capacity(h, C);
     const uint64_t words = chunks * 8;  // widest state: 8 words
-    const uint64_t lvl = lvl_capacity(h, C);
-    if (words <= h->ws_words && lvl <= h->lvl_words) return RNG_OK;
+    const uint64_t plan_bytes = plan_capacity(h, C);
+    if (words <= h->ws_words && plan_bytes <= h->plan_cap) return RNG_OK;
+    if (plan_bytes >= ((uint64_t)1 << 32)) return fail(RNG_ENOMEM, "batch plan above 4 GiB");
     if (chunks >= ((uint64_t)1 << 32)) return fail(RNG_ENOMEM, "more than 2^32 chunks of %llu samples",
                                                    (unsigned long long)C);
     for (auto &g : h->graphs) {
@@ -98,18 +106,21 @@ static int alloc_ws(rng_batch *h, uint64_t C)
     (void)hipDeviceSynchronize();  // no launch may still use the old buffers
     if (h->d_ws) (void)hipFree(h->d_ws);
     if (h->d_map) (void)hipFree(h->d_map);
-    if (h->d_lvl) (void)hipFree(h->d_lvl);
-    if (h->h_lvl) (void)hipHostFree(h->h_lvl);
-    h->d_ws = h->d_map = h->d_lvl = h->h_lvl = nullptr;
-    h->ws_words = h->lvl_words = 0;
+    if (h->d_plan) (void)hipFree(h->d_plan);
+    if (h->h_plan) (void)hipHostFree(h->h_plan);
+    h->d_ws = h->d_map = nullptr;
+    h->d_plan = h->h_plan = nullptr;
+    h->ws_words = h->plan_cap = 0;
+    h->planned = false;  // the plan lived in the old staging buffer
     hipError_t e;
     if ((e = hipMalloc((void **)&h->d_ws, words * 4)) != hipSuccess) return hip_fail(e, "hipMalloc(batch workspace)");
     if ((e = hipMalloc((void **)&h->d_map, chunks * 4)) != hipSuccess) return hip_fail(e, "hipMalloc(chunk map)");
-    if ((e = hipMalloc((void **)&h->d_lvl, lvl * 4)) != hipSuccess) return hip_fail(e, "hipMalloc(level lists)");
-    if ((e = hipHostMalloc((void **)&h->h_lvl, lvl * 4, hipHostMallocDefault)) != hipSuccess)
-        return hip_fail(e, "hipHostMalloc(level lists)");
+    if ((e = hipMalloc((void **)&h->d_plan, plan_bytes)) != hipSuccess) return hip_fail(e, "hipMalloc(batch plan)");
+    if ((e = hipHostMalloc((void **)&h->h_plan, plan_bytes, hipHostMallocDefault)) != hipSuccess)
+        return hip_fail(e, "hipHostMalloc(batch plan)");
+    std::memset(h->h_plan, 0, sizeof(BatchHeader));
     h->ws_words = words;
-    h->lvl_words = lvl;
+    h->plan_cap = plan_bytes;
     return RNG_OK;
 }
 
@@ -121,15 +132,11 @@ static void free_batch(rng_batch *h)
     }
     if (h->copied) (void)hipEventDestroy(h->copied);
     if (h->capture) (void)hipStreamDestroy(h->capture);
-    if (h->d_hdr) (void)hipFree(h->d_hdr);
-    if (h->d_reqs) (void)hipFree(h->d_reqs);
-    if (h->d_lvl) (void)hipFree(h->d_lvl);
+    if (h->d_plan) (void)hipFree(h->d_plan);
     if (h->d_map) (void)hipFree(h->d_map);
     if (h->d_ws) (void)hipFree(h->d_ws);
     if (h->d_counter) (void)hipFree(h->d_counter);
-    if (h->h_hdr) (void)hipHostFree(h->h_hdr);
-    if (h->h_reqs) (void)hipHostFree(h->h_reqs);
-    if (h->h_lvl) (void)hipHostFree(h->h_lvl);
+    if (h->h_plan) (void)hipHostFree(h->h_plan);
     delete h;
 }
 
@@ -142,10 +149,7 @@ static bool shape_ok(uint32_t wg, uint32_t unroll)
 static BatchArgs make_args(rng_batch *h, const DevTables &tab)
 {
     BatchArgs a{};
-    a.hdr = h->d_hdr;
-    a.reqs = h->d_reqs;
-    a.seg = (const uint2 *)h->d_lvl;
-    a.blk_first = h->d_lvl + 2 * seg_capacity(h);
+    a.hdr = (const BatchHeader *)h->d_plan;
     a.chunk_req = h->d_map;
     a.ws = h->d_ws;
     a.counter = h->d_counter;
@@ -172,11 +176,7 @@ int rng_batch_create(uint32_t max_requests, uint64_t max_samples, rng_batch_t **
     if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) h->num_cu = prop.multiProcessorCount;
     hipError_t e = hipSuccess;
     int rc = RNG_OK;
-    if ((e = hipMalloc((void **)&h->d_hdr, sizeof(BatchHeader))) != hipSuccess ||
-        (e = hipMalloc((void **)&h->d_reqs, sizeof(BatchReq) * max_requests)) != hipSuccess ||
-        (e = hipMalloc((void **)&h->d_counter, 256)) != hipSuccess ||
-        (e = hipHostMalloc((void **)&h->h_hdr, sizeof(BatchHeader), hipHostMallocDefault)) != hipSuccess ||
-        (e = hipHostMalloc((void **)&h->h_reqs, sizeof(BatchReq) * max_requests, hipHostMallocDefault)) != hipSuccess ||
+    if ((e = hipMalloc((void **)&h->d_counter, 256)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&h->copied, hipEventDisableTiming)) != hipSuccess ||
         (e = hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking)) != hipSuccess)
         rc = hip_fail(e, "rng_batch_create");
@@ -304,10 +304,13 @@ static int plan(rng_batch_t *h, const rng_request_t *reqs, uint32_t n)
     std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return key(x) < key(y); });
     const uint64_t C = h->C;
 
-    BatchHeader &H = *h->h_hdr;
+    h->planned = false;  // until this plan is complete: a failure below leaves nothing to launch
+    BatchHeader &H = h->hdr();
     std::memset(&H, 0, sizeof(H));
     H.C = C;
     H.n = n;
+    H.off_reqs = (uint32_t)align16(sizeof(BatchHeader));
+    BatchReq *Q = plan_at<BatchReq>(&H, H.off_reqs);
     uint64_t ws_off = 0, tiles = 0, max_chunks = 0;
     uint32_t i = 0;
     while (i < n) {
@@ -320,7 +323,7 @@ static int plan(rng_batch_t *h, const rng_request_t *reqs, uint32_t n)
         uint64_t chunks = 0;
         for (; i < n && key(order[i]) == k; ++i) {
             const rng_request_t &r = reqs[order[i]];
-            BatchReq &q = h->h_reqs[i];
+            BatchReq &q = Q[i];
             q.state = r.d_state;
             q.stride = r.state_stride;
             q.offset = r.offset;
@@ -352,37 +355,44 @@ static int plan(rng_batch_t *h, const rng_request_t *reqs, uint32_t n)
     if (levels > (uint32_t)kBatchMaxLevels) return fail(RNG_ERANGE, "a request needs more than 2^40 chunks");
     H.levels = levels;
     for (uint32_t g = 0; g < H.ngroups; ++g) H.has_xs256 |= H.groups[g].gen == (uint32_t)RNG_XS256;
-    uint2 *segs = (uint2 *)h->h_lvl;
-    uint32_t *blks = h->h_lvl + 2 * seg_capacity(h);
+    H.off_seg = (uint32_t)align16(H.off_reqs + sizeof(BatchReq) * (uint64_t)n);
+    uint2 *segs = plan_at<uint2>(&H, H.off_seg);
     const bool pow2 = (C & (C - 1)) == 0;
     const uint32_t lc = (uint32_t)__builtin_ctzll(C);
     uint32_t S = 0, B = 0;
     for (uint32_t l = 0; l < levels; ++l) {
         LevelInfo &L = H.lvl[l];
         L.seg_off = S;
-        L.blk_off = B;
         L.shift = kRadixBits * l;
         L.pow = pow2 && lc + L.shift + kRadixBits <= 64 ? lc + L.shift : 0xFFFFFFFFu;
         L.pad = 0;
         const uint64_t lo = (uint64_t)1 << L.shift, hi = lo << kRadixBits;
         uint64_t acc = 0;
         for (uint32_t r = 0; r < n; ++r) {
-            const uint64_t nc = h->h_reqs[r].nchunks;
+            const uint64_t nc = Q[r].nchunks;
             if (nc <= lo) continue;
             segs[S++] = make_uint2(r, (uint32_t)acc);
             acc += std::min(nc, hi) - lo;
         }
         L.seg_n = S - L.seg_off;
         H.level_total[l] = (uint32_t)acc;
+    }
+    // block starts after all segments: the segment of each level's block's first item
+    H.off_blk = (uint32_t)align16(H.off_seg + 8ull * S);
+    uint64_t nblk = 0;
+    for (uint32_t l = 0; l < levels; ++l) nblk += (H.level_total[l] + kLevelWG - 1) / kLevelWG;
+    if (H.off_blk + 4 * nblk > h->plan_cap) return fail(RNG_ENOMEM, "batch plan exceeds its buffer");
+    uint32_t *blks = plan_at<uint32_t>(&H, H.off_blk);
+    for (uint32_t l = 0; l < levels; ++l) {
+        LevelInfo &L = H.lvl[l];
+        L.blk_off = B;
         uint32_t k = 0;
-        for (uint64_t t0 = 0; t0 < acc; t0 += kLevelWG) {
+        for (uint64_t t0 = 0; t0 < H.level_total[l]; t0 += kLevelWG) {
             while (k + 1 < L.seg_n && segs[L.seg_off + k + 1].y <= t0) ++k;
             blks[B++] = k;
         }
     }
-    H.pad = 0;
-    h->n_seg = S;
-    h->n_blk = B;
+    H.plan_bytes = H.off_blk + 4 * B;
     h->planned = true;
     return RNG_OK;
 }
@@ -398,15 +408,10 @@ int rng_batch_launch(rng_batch_t *h, void *stream)
     DevTables tab;
     if (int rc = device_tables(&tab)) return rc;
     hipStream_t st = (hipStream_t)stream;
-    const BatchHeader &H = *h->h_hdr;
+    const BatchHeader &H = h->hdr();
     hipError_t e;
-    if ((e = hipMemcpyAsync(h->d_hdr, h->h_hdr, sizeof(BatchHeader), hipMemcpyHostToDevice, st)) != hipSuccess ||
-        (H.n && (e = hipMemcpyAsync(h->d_reqs, h->h_reqs, sizeof(BatchReq) * H.n, hipMemcpyHostToDevice, st)) !=
-                    hipSuccess) ||
-        (h->n_seg && (e = hipMemcpyAsync(h->d_lvl, h->h_lvl, 8ull * h->n_seg, hipMemcpyHostToDevice, st)) !=
-                         hipSuccess) ||
-        (h->n_blk && (e = hipMemcpyAsync(h->d_lvl + 2 * seg_capacity(h), h->h_lvl + 2 * seg_capacity(h),
-                                         4ull * h->n_blk, hipMemcpyHostToDevice, st)) != hipSuccess))
+    // the whole plan in one copy
+    if ((e = hipMemcpyAsync(h->d_plan, h->h_plan, H.plan_bytes, hipMemcpyHostToDevice, st)) != hipSuccess)
         return hip_fail(e, "rng_batch_launch: upload");
     if ((e = hipEventRecord(h->copied, st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     h->copy_pending = true;

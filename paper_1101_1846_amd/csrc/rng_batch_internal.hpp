@@ -60,7 +60,9 @@ struct LevelInfo {
 };
 
 // Per-batch header, rewritten before every launch (the captured graph only
-// holds pointers to it).
+// holds a pointer to it).  It heads the packed plan that one copy uploads:
+// the header, then the request table, the level segments and the block
+// starts, each at the byte offset the header gives (16-byte aligned).
 struct BatchHeader {
     uint64_t C;           // chunk length
     uint32_t n;           // requests
@@ -68,6 +70,10 @@ struct BatchHeader {
     uint32_t n_tiles;
     uint32_t levels;      // radix-16 tree levels used
     uint32_t has_xs256;   // some group is XS256 (its level's four tables are staged in LDS)
+    uint32_t off_reqs;    // BatchReq [n], sorted by group
+    uint32_t off_seg;     // uint2 level segments: (sorted request index, exclusive item prefix)
+    uint32_t off_blk;     // uint32 per level and kLevelWG-item block: segment (within the level) of its first item
+    uint32_t plan_bytes;  // bytes of the packed plan
     uint32_t pad;
     uint32_t level_total[kBatchMaxLevels];  // work items per level
     LevelInfo lvl[kBatchMaxLevels];
@@ -75,14 +81,17 @@ struct BatchHeader {
 };
 
 struct BatchArgs {
-    const BatchHeader *hdr;
-    const BatchReq *reqs;         // [n], sorted by group
-    const uint2 *seg;             // level segments: (sorted request index, exclusive item prefix)
-    const uint32_t *blk_first;    // per level and 256-item block: segment (within the level) of its first item
+    const BatchHeader *hdr;       // the packed plan
     uint32_t *chunk_req;          // [64 * n_tiles] sorted request index of every chunk (padded group order)
     uint32_t *ws;                 // chunk-state workspace
     uint32_t *counter;            // [0] tile counter of the persistent kernel
     DevTables tab;
 };
+
+template <class T>
+__host__ __device__ inline T *plan_at(const BatchHeader *p, uint32_t off)
+{
+    return (T *)((const char *)p + off);
+}
 
 }  // namespace rngx

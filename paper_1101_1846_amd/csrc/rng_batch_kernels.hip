@@ -42,9 +42,10 @@ __device__ __forceinline__ void with_gen(uint32_t g, F &&f)
 __global__ __launch_bounds__(256) void k_batch_root(BatchArgs a)
 {
     const BatchHeader &h = *a.hdr;
+    const BatchReq *reqs = plan_at<const BatchReq>(a.hdr, h.off_reqs);
     if (blockIdx.x == 0 && threadIdx.x == 0) a.counter[0] = 0;  // tile counter of the generation kernel
     for (uint32_t r = blockIdx.x * 256 + threadIdx.x; r < h.n; r += gridDim.x * 256) {
-        const BatchReq q = a.reqs[r];
+        const BatchReq q = reqs[r];
         const BatchGroup &gr = h.groups[q.group];
         uint32_t *qs = q.state;
         if (q.nchunks) a.chunk_req[gr.tile_begin * 64 + q.chunk_base] = r;
@@ -71,6 +72,9 @@ __global__ __launch_bounds__(kLevelWG) void k_batch_level(BatchArgs a, uint32_t 
     __shared__ uint32_t s_pre[kLevelWG], s_req[kLevelWG];
     const BatchHeader &h = *a.hdr;
     if (level >= h.levels) return;
+    const BatchReq *reqs = plan_at<const BatchReq>(a.hdr, h.off_reqs);
+    const uint2 *seg = plan_at<const uint2>(a.hdr, h.off_seg);
+    const uint32_t *blk_first = plan_at<const uint32_t>(a.hdr, h.off_blk);
     const LevelInfo L = h.lvl[level];
     const uint32_t total = h.level_total[level];
     const uint32_t nblk = (total + kLevelWG - 1) / kLevelWG;
@@ -83,10 +87,10 @@ __global__ __launch_bounds__(kLevelWG) void k_batch_level(BatchArgs a, uint32_t 
     }
     const uint32_t lo = 1u << L.shift;
     for (uint32_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-        const uint32_t k = a.blk_first[L.blk_off + blk] + threadIdx.x;
+        const uint32_t k = blk_first[L.blk_off + blk] + threadIdx.x;
         __syncthreads();  // the previous block's segments are consumed (and the tables are staged)
         if (k < L.seg_n) {
-            const uint2 sg = a.seg[L.seg_off + k];
+            const uint2 sg = seg[L.seg_off + k];
             s_req[threadIdx.x] = sg.x;
             s_pre[threadIdx.x] = sg.y;
         } else {
@@ -101,7 +105,7 @@ __global__ __launch_bounds__(kLevelWG) void k_batch_level(BatchArgs a, uint32_t 
         for (uint32_t step = kLevelWG / 2; step; step >>= 1)
             if (s_pre[i + step] <= t) i += step;
         const uint32_t r = s_req[i];
-        const BatchReq q = a.reqs[r];
+        const BatchReq q = reqs[r];
         const BatchGroup &gr = h.groups[q.group];
         const uint32_t j = lo + (t - s_pre[i]);  // chunk within the request
         const uint32_t rem = j & (lo - 1);       // the chunk it starts from
@@ -148,7 +152,8 @@ __device__ void batch_tile(const BatchArgs &a, const BatchGroup &gr, uint32_t ti
     const uint32_t c0 = (tile - gr.tile_begin) * 64;
     const bool active = c0 + lane < gr.nchunks;
     const uint32_t c = active ? c0 + lane : c0;
-    const BatchReq q = a.reqs[a.chunk_req[gr.tile_begin * 64 + c]];  // written by the root and tree kernels
+    // the chunk's request (the root and tree kernels wrote the map)
+    const BatchReq q = plan_at<const BatchReq>(a.hdr, h.off_reqs)[a.chunk_req[gr.tile_begin * 64 + c]];
     const uint64_t j = c - q.chunk_base;
     const uint64_t start = j * h.C;
     const uint32_t len = active ? (uint32_t)min<uint64_t>(h.C, q.length - start) : 0;
