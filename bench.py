@@ -191,7 +191,7 @@ def main():
         "per_kernel": {k: {kk: vv for kk, vv in v.items() if kk != "total_ms"} for k, v in per.items()},
         "side_workloads": extra,
         "served_latency_us": {k: {"p50": v["p50_us"], "p99": v["p99_us"]}
-                              for k, v in extra.get("served", {}).items()},
+                              for k, v in extra.get("served", {}).items() if isinstance(v, dict)},
         "cpu_baseline": cpu,
         "wall_s_timed": round(wall, 3),
     }
@@ -521,6 +521,11 @@ def batched_workload(torch, R, dev, reps=5):
             "shape": {"wg": wg, "unroll": un, "chunk": chunk}}
 
 
+# The server's worker keeps polling this long after its last activity before it
+# sleeps, so that a request arriving at low load finds it awake.
+SERVED_IDLE_SPIN_US = 2000
+
+
 def served_workload(R, single_rate):
     """Poisson arrivals at 2k, 20k and 200k requests/s over 10^6 resident streams
     (generator = stream id mod 3 over MWC32/XS256/KISS), sizes log-uniform in
@@ -528,8 +533,9 @@ def served_workload(R, single_rate):
     batches in flight; then a saturating burst of 20,000 requests."""
     from paper_1101_1846_amd import workloads as W
     gens = [R.GENERATORS[g] for g in ("MWC32", "XS256", "KISS")]
-    h = R.rng_server_create(10 ** 6, gens, 8, 16 << 30, 4096, 1 << 31, inflight=3, auto_release=True)
-    out = {}
+    h = R.rng_server_create(10 ** 6, gens, 8, 16 << 30, 4096, 1 << 31, inflight=3, auto_release=True,
+                            idle_spin_us=SERVED_IDLE_SPIN_US)
+    out = {"worker_idle_spin_us": SERVED_IDLE_SPIN_US}
     try:
         for lam, dur in ((2000, 1.0), (20000, 0.5), (200000, 0.25)):
             n = int(lam * dur)

@@ -282,8 +282,10 @@ int rng_batch_destroy(rng_batch_t *h);
 /* stream are served in arrival order, so request i of a stream returns the */
 /* samples [L_0 + ... + L_{i-1}, + L_i) of that stream's serial sequence.   */
 /* While batches are in flight the worker polls their events in a loop (it  */
-/* keeps one host core busy, for latency); it sleeps when none are.  Every  */
-/* batch picks its chunk length automatically (RNG_BATCH_CHUNK_AUTO).       */
+/* keeps one host core busy, for latency); when none are, it keeps polling  */
+/* for idle_spin_us after its last activity (so that a new request finds it */
+/* awake) and then sleeps until a submission wakes it.  Every batch picks   */
+/* its chunk length automatically (RNG_BATCH_CHUNK_AUTO).                   */
 /* ---------------------------------------------------------------------- */
 typedef struct {
     uint64_t n_streams;            /* resident streams; stream s runs gens[s % n_gens] */
@@ -296,6 +298,7 @@ typedef struct {
     uint64_t max_batch_samples;    /* per launched batch; also the largest request */
     uint32_t inflight;             /* batches in flight, 1..8 */
     uint32_t auto_release;         /* 1: free each output as soon as it completes */
+    uint32_t idle_spin_us;         /* idle polling window before the worker sleeps (0: sleep at once) */
 } rng_server_config_t;
 
 typedef struct {

@@ -86,7 +86,7 @@ class rng_server_config_t(ctypes.Structure):
     _fields_ = [("n_streams", ctypes.c_uint64), ("gens", ctypes.c_int32 * 5), ("n_gens", ctypes.c_uint32),
                 ("seed", ctypes.c_uint64), ("pool_bytes", ctypes.c_uint64), ("max_batch_requests", ctypes.c_uint32),
                 ("max_batch_samples", ctypes.c_uint64), ("inflight", ctypes.c_uint32),
-                ("auto_release", ctypes.c_uint32)]
+                ("auto_release", ctypes.c_uint32), ("idle_spin_us", ctypes.c_uint32)]
 
 
 class rng_server_stats_t(ctypes.Structure):
@@ -316,7 +316,7 @@ def rng_batch_destroy(h):
 
 
 def rng_server_create(n_streams, gens, seed, pool_bytes, max_batch_requests, max_batch_samples,
-                      inflight=3, auto_release=False):
+                      inflight=3, auto_release=False, idle_spin_us=0):
     cfg = rng_server_config_t()
     cfg.n_streams = n_streams
     for i, g in enumerate(gens):
@@ -328,6 +328,7 @@ def rng_server_create(n_streams, gens, seed, pool_bytes, max_batch_requests, max
     cfg.max_batch_samples = max_batch_samples
     cfg.inflight = inflight
     cfg.auto_release = 1 if auto_release else 0
+    cfg.idle_spin_us = idle_spin_us
     h = ctypes.c_void_p()
     _check(_lib.rng_server_create(ctypes.byref(cfg), ctypes.byref(h)), "rng_server_create")
     return h.value

@@ -128,6 +128,8 @@ static void worker_loop(rng_server *h)
     std::vector<rng_request_t> table;
     std::vector<uint64_t> chosen;
     std::unordered_set<uint64_t> in_batch;
+    const auto spin = std::chrono::microseconds(h->cfg.idle_spin_us);
+    auto last_active = Clock::now();
     while (true) {
         bool progressed = false;
         // completions
@@ -223,16 +225,18 @@ static void worker_loop(rng_server *h)
                 progressed = true;
             }
         }
-        if (!progressed) {
+        if (progressed) {
+            last_active = Clock::now();
+        } else {
             std::unique_lock<std::mutex> lk(h->mu);
             bool inflight = false;
             for (auto &s : h->slots) inflight |= s.busy;
             if (h->stop && h->pending.empty() && !inflight) break;
-            if (!inflight) {
+            if (!inflight && Clock::now() - last_active >= spin) {
                 h->cv_work.wait_for(lk, std::chrono::microseconds(200));
             } else {
                 lk.unlock();
-                std::this_thread::yield();  // keep polling the in-flight batches' events
+                std::this_thread::yield();  // keep polling: in-flight events, or new requests while idle
             }
         }
     }
@@ -245,6 +249,7 @@ int rng_server_create(const rng_server_config_t *cfg, rng_server_t **out)
     if (!cfg || !out) return fail(RNG_EINVAL, "NULL argument");
     if (cfg->n_streams == 0 || cfg->n_gens == 0 || cfg->n_gens > 5) return fail(RNG_EINVAL, "bad stream/generator count");
     if (cfg->inflight == 0 || cfg->inflight > 8) return fail(RNG_EINVAL, "inflight must be 1..8");
+    if (cfg->idle_spin_us > 1000000) return fail(RNG_EINVAL, "idle_spin_us above one second");
     if (cfg->max_batch_requests == 0 || cfg->max_batch_samples == 0 || cfg->pool_bytes < 256)
         return fail(RNG_EINVAL, "empty batch or pool limits");
     for (uint32_t k = 0; k < cfg->n_gens; ++k)

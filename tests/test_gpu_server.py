@@ -49,11 +49,14 @@ def _expected_per_stream(oracle, n_streams, seed, streams, lengths):
     return seq, fin
 
 
-def test_server_results_are_ordered_stream_slices(rng, hip, oracle):
+@pytest.mark.parametrize("idle_spin_us", [0, 2000])
+def test_server_results_are_ordered_stream_slices(rng, hip, oracle, idle_spin_us):
+    """With the worker sleeping whenever it is idle, and polling for 2 ms first."""
     from paper_1101_1846_amd import workloads as W
     n_streams, seed, n = 30, 8, 1500
     gens = [rng.GENERATORS[k] for k in KINDS]
-    h = rng.rng_server_create(n_streams, gens, seed, 1 << 30, 512, 1 << 22, inflight=3, auto_release=False)
+    h = rng.rng_server_create(n_streams, gens, seed, 1 << 30, 512, 1 << 22, inflight=3, auto_release=False,
+                              idle_spin_us=idle_spin_us)
     try:
         r = np.random.default_rng(12)
         t = W.poisson_arrivals(50_000, n, seed=13)
@@ -109,6 +112,8 @@ def test_server_admission_under_memory_pressure(rng, oracle):
 
 def test_server_argument_errors(rng):
     gens = [rng.GENERATORS[k] for k in KINDS]
+    with pytest.raises(rng.RngError):
+        rng.rng_server_create(9, gens, 1, 1 << 20, 16, 1 << 12, inflight=1, idle_spin_us=2_000_000)
     h = rng.rng_server_create(9, gens, 1, 1 << 20, 16, 1 << 12, inflight=1)
     try:
         L = rng.raw()
