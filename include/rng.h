@@ -256,11 +256,12 @@ int rng_batch_launch(rng_batch_t *h, void *stream);
 /* Persistent-kernel shape: wg lanes per workgroup (64..512), unroll
  * (samples per generation step) and chunk length C (a multiple of 64);
  * 0 keeps the current value.  chunk = RNG_BATCH_CHUNK_AUTO lets every plan
- * choose C: the power of two in [256, 4096] (larger minimum for handles of
- * more than 2^36 samples) that cuts the batch into about 2^17 chunks (as
- * many 64-chunk tiles as the device holds waves), so that small batches
- * still spread over the device.  A changed C applies to
- * the last planned table at once (it is planned again). */
+ * choose C: the power of two in [64, 4096] that cuts the batch into about
+ * 2^17 chunks (as many 64-chunk tiles as the device holds waves), so that
+ * small batches still spread over the device; the workspace is sized for
+ * 256-sample chunks (more for handles of more than 2^36 samples), and a plan
+ * goes below that only while its chunks fit.  A changed C applies to the
+ * last planned table at once (it is planned again). */
 #define RNG_BATCH_CHUNK_AUTO 0xFFFFFFFFu
 int rng_batch_set_shape(rng_batch_t *h, uint32_t wg, uint32_t unroll, uint32_t chunk);
 /* The current shape; chunk reads RNG_BATCH_CHUNK_AUTO in automatic mode. */

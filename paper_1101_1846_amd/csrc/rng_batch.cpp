@@ -50,10 +50,14 @@ struct rng_batch {
     BatchHeader &hdr() { return *(BatchHeader *)h_plan; }
 };
 
-// Automatic chunk length: a power of two in [min, 4096] that cuts the batch
+// Automatic chunk length: a power of two in [64, 4096] that cuts the batch
 // into about 2^17 chunks (2048 tiles of 64: the waves the device holds at
-// once), so that a small batch still spreads over the device.
+// once), so that a small batch still spreads over the device.  The workspace
+// is sized for chunks of auto_chunk_min (256, more for huge handles); shorter
+// chunks are taken only while the plan's chunks fit it.
 constexpr uint64_t kAutoChunkMax = 4096;
+constexpr uint64_t kAutoChunkFloor = kBatchTile;
+constexpr uint64_t kSmallBatch = (uint64_t)1 << 19;  // samples
 constexpr uint64_t kAutoChunks = (uint64_t)1 << 17;
 static uint64_t auto_chunk_min(uint64_t max_samples)
 {
@@ -286,8 +290,14 @@ static int plan(rng_batch_t *h, const rng_request_t *reqs, uint32_t n)
         return fail(RNG_ENOMEM, "batch of %llu samples > capacity %llu", (unsigned long long)total_samples,
                     (unsigned long long)h->max_samples);
     if (h->chunk_auto) {
-        uint64_t c = auto_chunk_min(h->max_samples);
-        while (c < kAutoChunkMax && total_samples / (2 * c) >= kAutoChunks) c *= 2;
+        // The workspace holds max_samples in chunks of auto_chunk_min.  A
+        // small batch (its time is the serial work per lane) takes shorter
+        // chunks, down to one 64-sample tile, while they fit; larger ones keep
+        // the longer minimum, since more chunks mean more tree work.
+        const uint64_t cmin = auto_chunk_min(h->max_samples), fit = (h->max_samples + cmin - 1) / cmin;
+        uint64_t c = total_samples <= kSmallBatch ? kAutoChunkFloor : cmin;
+        while (c < kAutoChunkMax && (total_samples / (2 * c) >= kAutoChunks || (total_samples + c - 1) / c > fit))
+            c *= 2;
         h->C = c;
     }
     // The pinned staging buffers are about to be rewritten: wait for the

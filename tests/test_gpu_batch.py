@@ -208,6 +208,33 @@ def test_batch_graph_replays(rng, torch, oracle):
         rng.rng_batch_destroy(h)
 
 
+def test_batch_plans_of_different_sizes(rng, torch, oracle):
+    """Plans of very different sizes on one handle (different tree depths and
+    tile counts): a one-request plan, a 200-request plan with long requests,
+    then the small one again.  Each run is checked against the oracle's pass
+    over those streams."""
+    m = Mix(rng, torch, oracle, 200, seed=31, max_len=60000, offsets=False)
+    h = rng.rng_batch_create(256, 1 << 24)
+    try:
+        rng.rng_batch_set_shape(h, 0, 0, 64)  # many chunks per request: several tree levels
+        runs = {i: 0 for i in range(200)}
+        for subset in ([7], list(range(200)), [7]):
+            rng.rng_batch_set(h, m.requests(subset))
+            rng.rng_batch_launch(h)
+            torch.cuda.synchronize()
+            for i in subset:
+                runs[i] += 1
+            got = _u32(m.out)
+            pools = {g: _u32(p) for g, p in m.pool.items()}
+            for i in subset:
+                exp, st = m.expected(i, runs[i])
+                n = int(m.length[i])
+                assert np.array_equal(got[m.offs[i]:m.offs[i] + n], exp), (subset[:3], i)
+                assert np.array_equal(pools[m.gen[i]][:, m.idx[i]], st), (i, "state")
+    finally:
+        rng.rng_batch_destroy(h)
+
+
 def test_batch_validation(rng, torch):
     h = rng.rng_batch_create(4, 1000)
     st = torch.empty(8, dtype=torch.int32, device="cuda")
