@@ -237,9 +237,10 @@ def write_ceiling(torch, dev):
     return res
 
 
-def _time(torch, fn, reps):
+def _time(torch, fn, reps, warm=1):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    fn()
+    for _ in range(warm):
+        fn()
     torch.cuda.synchronize()
     e0.record()
     for _ in range(reps):
@@ -478,11 +479,12 @@ def batch_pools(torch, R, dev, tab, seed=5):
     return pools, where
 
 
-def batched_workload(torch, R, dev, reps=5):
+def batched_workload(torch, R, dev, reps=10):
     """10,000 independent requests (generator uniform over MWC32/XS256/KISS,
-    dtype 50/50, length log-uniform in [2^8, 2^22]) in one persistent launch
-    replayed from a HIP graph; compared with the same samples generated by one
-    large rng_generate call per (generator, dtype)."""
+    dtype 50/50, length log-uniform in [2^8, 2^22]) in one persistent
+    generation launch, its kernels launched directly (and, for comparison,
+    replayed from a captured HIP graph); compared with the same samples
+    generated by one large rng_generate call per (generator, dtype)."""
     from paper_1101_1846_amd import workloads as W
     tab = W.batch_table(10000, seed=4)
     names = tab["generators"]
@@ -497,7 +499,16 @@ def batched_workload(torch, R, dev, reps=5):
     try:
         R.rng_batch_set(h, reqs)
         wg, un, chunk, tune_us = R.rng_batch_autotune(h, reps=1)
+        # the generation kernel takes 6-8 launches of a new plan to settle
+        # (3.6 -> 3.15 ms in a kernel trace, in either launch mode): both
+        # modes are warmed before either is timed
+        for use_graph in (False, True):
+            R.rng_batch_set_graph(h, use_graph)
+            _time(torch, lambda: R.rng_batch_launch(h), 4, warm=4)
+        R.rng_batch_set_graph(h, False)
         ms = _time(torch, lambda: R.rng_batch_launch(h), reps)
+        R.rng_batch_set_graph(h, True)
+        graph_ms = _time(torch, lambda: R.rng_batch_launch(h), reps)
     finally:
         R.rng_batch_destroy(h)
     # single large calls over the same per-(generator, dtype) sample counts
@@ -518,7 +529,7 @@ def batched_workload(torch, R, dev, reps=5):
     return {"requests": len(reqs), "samples": total, "bytes": 4 * total, "ms_per_batch": round(ms, 3),
             "GSamples_s": round(rate, 1), "GB_s": round(4 * total / (ms * 1e-3) / 1e9, 1),
             "single_large_call_GSamples_s": round(single, 1), "frac_of_single_call": round(rate / single, 4),
-            "shape": {"wg": wg, "unroll": un, "chunk": chunk}}
+            "graph_replay_ms_per_batch": round(graph_ms, 3), "shape": {"wg": wg, "unroll": un, "chunk": chunk}}
 
 
 # The server's worker keeps polling this long after its last activity before it

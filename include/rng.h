@@ -214,14 +214,15 @@ int rng_xs256_placement(int placement, uint32_t *d_state, uint64_t n_streams, ui
 
 /* ---------------------------------------------------------------------- */
 /* Batched generation: thousands of independent requests of uneven length  */
-/* in one persistent launch captured in a HIP graph.  Each request is the   */
+/* in one persistent generation launch (after the root and tree launches,   */
+/* issued directly or replayed as a captured HIP graph).  Each request is a */
 /* slice [offset, offset + length) of one stream's serial sequence; the     */
 /* stream's state is advanced by offset + length.  Requests are cut into    */
 /* chunks of C samples whose start states come from jump-ahead: one jump    */
 /* per request, then a radix-16 tree (level l starts chunk q 16^l + r from  */
-/* chunk r, q < 16: at most four jumps by powers of two per chunk, one      */
-/* launch per level); a persistent kernel pulls 64-chunk tiles from an      */
-/* atomic counter.                                                          */
+/* chunk r, q < 16: at most four jumps by powers of two per chunk; level 0  */
+/* in the root's launch, one launch per further level); a persistent kernel */
+/* pulls 64-chunk tiles from an atomic counter.                             */
 /* ---------------------------------------------------------------------- */
 typedef struct {
     int32_t gen;            /* rng_gen_t */
@@ -250,9 +251,17 @@ int rng_batch_create(uint32_t max_requests, uint64_t max_samples, rng_batch_t **
  * twice is RNG_EINVAL; overlapping strided states are not detected).  Blocks
  * until the previous launch's plan upload has left the staging buffers. */
 int rng_batch_set(rng_batch_t *h, const rng_request_t *h_reqs, uint32_t n);
-/* Queue the planned batch on stream: plan upload, then the graph (root
- * jumps, tree levels, persistent generation). */
+/* Queue the planned batch on stream: one plan upload, then the root jumps
+ * (with tree level 0), the further tree levels and the persistent
+ * generation kernel. */
 int rng_batch_launch(rng_batch_t *h, void *stream);
+/* use_graph = 1: rng_batch_launch replays a HIP graph of those kernels,
+ * captured once per (tree depth, shape) on the handle's own stream;
+ * 0 (the default): it launches them directly.  Both give the same results.
+ * On MI355X with ROCm 7 a graph replay of 2-6 kernels costs about 21 us of
+ * host time against 2.6 us per direct launch, so the direct launches give
+ * the lower latency. */
+int rng_batch_set_graph(rng_batch_t *h, int use_graph);
 /* Persistent-kernel shape: wg lanes per workgroup (64..512), unroll
  * (samples per generation step) and chunk length C (a multiple of 64);
  * 0 keeps the current value.  chunk = RNG_BATCH_CHUNK_AUTO lets every plan

@@ -75,6 +75,7 @@ _SIGS.update({
     "rng_batch_set": (_int, [_vp, ctypes.POINTER(rng_request_t), _u32]),
     "rng_batch_launch": (_int, [_vp, _vp]),
     "rng_batch_set_shape": (_int, [_vp, _u32, _u32, _u32]),
+    "rng_batch_set_graph": (_int, [_vp, ctypes.c_int]),
     "rng_batch_get_shape": (_int, [_vp, _pu32, _pu32, _pu32]),
     "rng_batch_destroy": (_int, [_vp]),
     "rng_batch_autotune": (_int, [_vp, _u32, _pu32, _pu32, _pu32, ctypes.POINTER(ctypes.c_float), _vp]),
@@ -296,6 +297,10 @@ def rng_batch_launch(h, stream=None):
 
 def rng_batch_set_shape(h, wg=0, unroll=0, chunk=0):
     return _check(_lib.rng_batch_set_shape(h, wg, unroll, chunk), "rng_batch_set_shape")
+
+
+def rng_batch_set_graph(h, use_graph):
+    return _check(_lib.rng_batch_set_graph(h, 1 if use_graph else 0), "rng_batch_set_graph")
 
 
 def rng_batch_get_shape(h):

@@ -45,6 +45,9 @@ struct rng_batch {
         hipGraphExec_t exec;
     };
     std::vector<Graph> graphs;
+    bool use_graph = false;               // replay a captured graph instead of launching directly
+    uint32_t occ_wg = 0, occ_unroll = 0;  // shape of the cached occupancy
+    unsigned gen_full = 0;                // generation workgroups resident at once for that shape
     int num_cu = 256;
     std::vector<rng_request_t> last;  // last planned table, re-planned on a chunk change
     BatchHeader &hdr() { return *(BatchHeader *)h_plan; }
@@ -230,6 +233,15 @@ int rng_batch_set_shape(rng_batch_t *h, uint32_t wg, uint32_t unroll, uint32_t c
     return RNG_OK;
 }
 
+int rng_batch_set_graph(rng_batch_t *h, int use_graph)
+{
+    if (!h) return fail(RNG_EINVAL, "NULL handle");
+    if (use_graph != 0 && use_graph != 1) return fail(RNG_EINVAL, "use_graph must be 0 or 1");
+    std::lock_guard<std::mutex> lk(h->mu);
+    h->use_graph = use_graph == 1;
+    return RNG_OK;
+}
+
 int rng_batch_get_shape(rng_batch_t *h, uint32_t *wg, uint32_t *unroll, uint32_t *chunk)
 {
     if (!h || !wg || !unroll || !chunk) return fail(RNG_EINVAL, "NULL argument");
@@ -370,7 +382,7 @@ static int plan(rng_batch_t *h, const rng_request_t *reqs, uint32_t n)
     const bool pow2 = (C & (C - 1)) == 0;
     const uint32_t lc = (uint32_t)__builtin_ctzll(C);
     uint32_t S = 0, B = 0;
-    for (uint32_t l = 0; l < levels; ++l) {
+    for (uint32_t l = 1; l < levels; ++l) {  // level 0 is done by the root kernel
         LevelInfo &L = H.lvl[l];
         L.seg_off = S;
         L.shift = kRadixBits * l;
@@ -390,10 +402,10 @@ static int plan(rng_batch_t *h, const rng_request_t *reqs, uint32_t n)
     // block starts after all segments: the segment of each level's block's first item
     H.off_blk = (uint32_t)align16(H.off_seg + 8ull * S);
     uint64_t nblk = 0;
-    for (uint32_t l = 0; l < levels; ++l) nblk += (H.level_total[l] + kLevelWG - 1) / kLevelWG;
+    for (uint32_t l = 1; l < levels; ++l) nblk += (H.level_total[l] + kLevelWG - 1) / kLevelWG;
     if (H.off_blk + 4 * nblk > h->plan_cap) return fail(RNG_ENOMEM, "batch plan exceeds its buffer");
     uint32_t *blks = plan_at<uint32_t>(&H, H.off_blk);
-    for (uint32_t l = 0; l < levels; ++l) {
+    for (uint32_t l = 1; l < levels; ++l) {
         LevelInfo &L = H.lvl[l];
         L.blk_off = B;
         uint32_t k = 0;
@@ -426,15 +438,28 @@ int rng_batch_launch(rng_batch_t *h, void *stream)
     if ((e = hipEventRecord(h->copied, st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     h->copy_pending = true;
 
+    if (h->occ_wg != h->wg || h->occ_unroll != h->unroll) {
+        int per_cu = 0;
+        if (batch_gen_occupancy((int)h->wg, (int)h->unroll, &per_cu) || per_cu <= 0) per_cu = 1;
+        h->gen_full = (unsigned)(h->num_cu * per_cu);
+        h->occ_wg = h->wg;
+        h->occ_unroll = h->unroll;
+    }
+    const unsigned gen_grid = h->gen_full;
+    const unsigned level_grid =
+        (unsigned)std::min<uint64_t>((chunk_capacity(h, h->C) + kLevelWG - 1) / kLevelWG, 256);
+    if (!h->use_graph) {
+        // root (and tree level 0), the further tree levels, persistent generation
+        const BatchArgs a = make_args(h, tab);
+        int rc = launch_batch_root(a, h->max_requests, st);
+        for (uint32_t l = 1; !rc && l < H.levels; ++l) rc = launch_batch_level(a, l, level_grid, st);
+        if (!rc) rc = launch_batch_gen(a, (int)h->wg, (int)h->unroll, gen_grid, st);
+        return check_launch(rc, "rng_batch_launch");
+    }
     rng_batch::Graph *gp = nullptr;
     for (auto &g : h->graphs)
         if (g.levels == H.levels && g.wg == h->wg && g.unroll == h->unroll) gp = &g;
     if (!gp) {
-        int per_cu = 0;
-        if (batch_gen_occupancy((int)h->wg, (int)h->unroll, &per_cu) || per_cu <= 0) per_cu = 1;
-        const unsigned gen_grid = (unsigned)(h->num_cu * per_cu);
-        const uint64_t cap = chunk_capacity(h, h->C);
-        const unsigned level_grid = (unsigned)std::min<uint64_t>((cap + kLevelWG - 1) / kLevelWG, 256);
         const BatchArgs a = make_args(h, tab);
         rng_batch::Graph g{H.levels, h->wg, h->unroll, nullptr, nullptr};
         // Recorded on the handle's own stream (the caller's may be the null
@@ -443,7 +468,8 @@ int rng_batch_launch(rng_batch_t *h, void *stream)
         if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return hip_fail(e, "hipStreamBeginCapture");
         int rc = launch_batch_root(a, h->max_requests, cs);
-        for (uint32_t l = 0; !rc && l < H.levels; ++l) rc = launch_batch_level(a, l, level_grid, cs);
+        // level 0 (chunks 1..15 of every request) is done by the root kernel
+        for (uint32_t l = 1; !rc && l < H.levels; ++l) rc = launch_batch_level(a, l, level_grid, cs);
         if (!rc) rc = launch_batch_gen(a, (int)h->wg, (int)h->unroll, gen_grid, cs);
         e = hipStreamEndCapture(cs, &g.graph);
         if (rc) {

@@ -42,8 +42,8 @@ struct BatchGroup {
 // start state.  Level l covers the chunks j in [16^l, 16^(l+1)) of every
 // request with more than 16^l chunks: with j = q 16^l + r (q in 1..15,
 // r < 16^l), chunk j starts where chunk r starts, jumped by q 16^l C samples
-// (level 0: chunk j < 16 from chunk 0, by j C).  Those requests are the
-// level's segments, in table order, each with the exclusive prefix of the
+// (level 0, chunk j < 16 from chunk 0 by j C, is done by the root kernel and
+// has no work list).  Those requests are the level's segments, in table order, each with the exclusive prefix of the
 // work items before it.  Items are handled in blocks of kLevelWG; the block
 // start table gives the segment holding each block's first item, so that a
 // block needs only its kLevelWG following segments.

@@ -36,30 +36,54 @@ __device__ __forceinline__ void with_gen(uint32_t g, F &&f)
     }
 }
 
-// Root of each request's tree: its state jumped by `offset` becomes the start
-// of chunk 0 (or, for an empty request, is written straight back).  Also
-// clears the generation kernel's tile counter.
-__global__ __launch_bounds__(256) void k_batch_root(BatchArgs a)
+// Root of each request's tree and its first level, 16 lanes per request:
+// the leading lane jumps the request's state by `offset` (the start of chunk
+// 0, or, for an empty request, the state written straight back) and passes it
+// through LDS to the other 15, and lane j < nchunks starts chunk j from it,
+// jumped by j C (level 0 of the radix-16 tree).  Also clears the generation
+// kernel's tile counter.
+constexpr int kRootWG = 256;
+
+__global__ __launch_bounds__(kRootWG) void k_batch_root(BatchArgs a)
 {
+    __shared__ uint32_t s_st[8 * kRootWG];  // leader states, [word][lane]
     const BatchHeader &h = *a.hdr;
     const BatchReq *reqs = plan_at<const BatchReq>(a.hdr, h.off_reqs);
     if (blockIdx.x == 0 && threadIdx.x == 0) a.counter[0] = 0;  // tile counter of the generation kernel
-    for (uint32_t r = blockIdx.x * 256 + threadIdx.x; r < h.n; r += gridDim.x * 256) {
-        const BatchReq q = reqs[r];
+    const uint32_t j = threadIdx.x & 15, lead = threadIdx.x & ~15u;
+    // uniform over the workgroup: every lane takes part in each barrier
+    for (uint32_t base = blockIdx.x * kRootWG; base < h.n * 16; base += gridDim.x * kRootWG) {
+        const uint32_t r = (base + threadIdx.x) >> 4;
+        const bool live = r < h.n;
+        const BatchReq q = reqs[live ? r : 0];
         const BatchGroup &gr = h.groups[q.group];
-        uint32_t *qs = q.state;
-        if (q.nchunks) a.chunk_req[gr.tile_begin * 64 + q.chunk_base] = r;
-        with_gen(gr.gen, [&]<class G>() {
-            G g;
-            g.load(qs, q.stride, 0, a.tab);
-            if (q.offset) g.jump(q.offset, a.tab);
-            if (q.nchunks == 0) g.store(qs, q.stride, 0);
-            else g.store(a.ws + gr.ws_off, gr.nchunks_pad, q.chunk_base);
-        });
+        if (live && j == 0) {
+            if (q.nchunks) a.chunk_req[gr.tile_begin * 64 + q.chunk_base] = r;
+            with_gen(gr.gen, [&]<class G>() {
+                G g;
+                g.load(q.state, q.stride, 0, a.tab);
+                if (q.offset) g.jump(q.offset, a.tab);
+                if (q.nchunks == 0) g.store(q.state, q.stride, 0);
+                else g.store(a.ws + gr.ws_off, gr.nchunks_pad, q.chunk_base);
+                g.store(s_st, kRootWG, threadIdx.x);
+            });
+        }
+        __syncthreads();
+        if (live && j > 0 && j < q.nchunks) {
+            const uint32_t c = q.chunk_base + j;
+            a.chunk_req[gr.tile_begin * 64 + c] = r;
+            with_gen(gr.gen, [&]<class G>() {
+                G g;
+                g.load(s_st, kRootWG, lead, a.tab);
+                g.jump((uint64_t)j * h.C, a.tab);
+                g.store(a.ws + gr.ws_off, gr.nchunks_pad, c);
+            });
+        }
+        __syncthreads();  // the leaders' LDS slots are read before the next round writes them
     }
 }
 
-// Level l of the radix-16 tree: chunk j in [16^l, min(16^(l+1), nchunks)) of
+// Level l >= 1 of the radix-16 tree: chunk j in [16^l, min(16^(l+1), nchunks)) of
 // every request, j = q 16^l + r, starts where chunk r starts, jumped by
 // q 16^l C.  A block takes kLevelWG consecutive work items: it loads the
 // kLevelWG segments from its first item's segment on (a block spans at most
@@ -267,8 +291,9 @@ __global__ __launch_bounds__(WG) void k_batch_gen(BatchArgs a)
 // ------------------------------------------------------------------ launchers
 int launch_batch_root(const BatchArgs &a, uint32_t max_requests, hipStream_t s)
 {
-    unsigned grid = (max_requests + 255) / 256;
-    hipLaunchKernelGGL(k_batch_root, dim3(grid ? grid : 1), dim3(256), 0, s, a);
+    const uint64_t lanes = (uint64_t)max_requests * 16, blocks = (lanes + kRootWG - 1) / kRootWG;
+    const unsigned grid = (unsigned)(blocks < 1024 ? blocks : 1024);
+    hipLaunchKernelGGL(k_batch_root, dim3(grid ? grid : 1), dim3(kRootWG), 0, s, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -187,11 +187,14 @@ def test_batch_auto_chunk(rng, torch, oracle, n, max_len):
         rng.rng_batch_destroy(h)
 
 
-def test_batch_graph_replays(rng, torch, oracle):
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_graph_replays(rng, torch, oracle, use_graph):
     """The same plan launched three times, with eager library work and a
-    synchronisation between replays: replay k must give pass k of every stream."""
+    synchronisation between replays: replay k must give pass k of every stream
+    (kernels launched directly, and replayed from the captured graph)."""
     m = Mix(rng, torch, oracle, 50, seed=5, max_len=5000, offsets=False)
     h = rng.rng_batch_create(64, 1 << 20)
+    rng.rng_batch_set_graph(h, use_graph)
     side = torch.empty((1, 4096), dtype=torch.int32, device="cuda")
     side_out = torch.empty(4096 * 64, dtype=torch.int32, device="cuda")
     try:
@@ -208,13 +211,15 @@ def test_batch_graph_replays(rng, torch, oracle):
         rng.rng_batch_destroy(h)
 
 
-def test_batch_plans_of_different_sizes(rng, torch, oracle):
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_plans_of_different_sizes(rng, torch, oracle, use_graph):
     """Plans of very different sizes on one handle (different tree depths and
     tile counts): a one-request plan, a 200-request plan with long requests,
     then the small one again.  Each run is checked against the oracle's pass
     over those streams."""
     m = Mix(rng, torch, oracle, 200, seed=31, max_len=60000, offsets=False)
     h = rng.rng_batch_create(256, 1 << 24)
+    rng.rng_batch_set_graph(h, use_graph)
     try:
         rng.rng_batch_set_shape(h, 0, 0, 64)  # many chunks per request: several tree levels
         runs = {i: 0 for i in range(200)}
@@ -263,6 +268,7 @@ def test_batch_validation(rng, torch):
         too_long = rng.make_requests([(rng.RNG_XS32, 0, st, 1, 0, 1001, out)])
         assert L.rng_batch_set(h, too_long, 1) == rng.RNG_ENOMEM
         assert L.rng_batch_set_shape(h, 96, 8, 0) == rng.RNG_EINVAL
+        assert L.rng_batch_set_graph(h, 2) == rng.RNG_EINVAL
         assert L.rng_batch_set_shape(h, 256, 8, 100) == rng.RNG_EINVAL
         del ctypes
     finally:
