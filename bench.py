@@ -294,8 +294,25 @@ def small_workloads(torch, R, dev):
     wg, un, _ = R.rng_autotune(g, R.RNG_U32, S, N, scratch, o, 5)
     R.rng_set_shape(g, R.RNG_U32, *prev)
     ms = _time(torch, lambda: R.rng_generate_ex(g, st, S, N, R.RNG_U32, o, wg, un), 200)
+    # the same call 100 times in one captured HIP graph: the device time per
+    # call without the host's launch overhead
+    calls = 100
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(cs):
+        R.rng_generate_ex(g, st, S, N, R.RNG_U32, o, wg, un, cs)  # outside the capture: lazy set-up
+        torch.cuda.synchronize()
+        with torch.cuda.graph(gr, stream=cs):
+            for _ in range(calls):
+                R.rng_generate_ex(g, st, S, N, R.RNG_U32, o, wg, un, cs)
+    torch.cuda.synchronize()
+    graph_ms = _time(torch, gr.replay, 10) / calls
+    del gr
     res["mwc32_4096x1024"] = {"us_per_call": round(ms * 1e3, 2), "wg": wg, "unroll": un,
-                              "GSamples_s": round(S * N / (ms * 1e-3) / 1e9, 1)}
+                              "GSamples_s": round(S * N / (ms * 1e-3) / 1e9, 1),
+                              "us_per_call_in_graph": round(graph_ms * 1e3, 2),
+                              "GSamples_s_in_graph": round(S * N / (graph_ms * 1e-3) / 1e9, 1)}
     for name in ("MWC1616", "MWC32"):
         g = R.GENERATORS[name]
         st = torch.empty((R.rng_state_words(g), S_BULK), dtype=torch.int32, device=dev)
