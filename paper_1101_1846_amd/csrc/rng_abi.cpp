@@ -36,14 +36,13 @@ int hip_fail(hipError_t e, const char *what)
 
 // ---------------------------------------------------------------- tables
 namespace {
-constexpr int kMaxDev = 64;
 struct DevEntry {
     bool ready = false;
     void *blob = nullptr;
     DevTables tab{};
 };
 std::mutex g_mu;
-DevEntry g_dev[kMaxDev];
+DevEntry g_dev[kMaxDevices];
 }  // namespace
 
 int device_tables(DevTables *out)
@@ -51,7 +50,7 @@ int device_tables(DevTables *out)
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    if (dev < 0 || dev >= kMaxDev) return fail(RNG_ENODEV, "device %d out of range", dev);
+    if (dev < 0 || dev >= kMaxDevices) return fail(RNG_ENODEV, "device %d out of range", dev);
     std::lock_guard<std::mutex> lk(g_mu);
     DevEntry &d = g_dev[dev];
     if (!d.ready) {
@@ -102,7 +101,7 @@ int shutdown_tables()
     std::lock_guard<std::mutex> lk(g_mu);
     int cur = 0;
     (void)hipGetDevice(&cur);
-    for (int i = 0; i < kMaxDev; ++i) {
+    for (int i = 0; i < kMaxDevices; ++i) {
         if (!g_dev[i].ready) continue;
         (void)hipSetDevice(i);
         (void)hipFree(g_dev[i].blob);

@@ -35,6 +35,9 @@ __host__ __device__ constexpr bool chunks_in_workgroup(uint32_t P, int nw) { ret
 // caller advances them by N with a skip launch).
 constexpr int kStatesNotWritten = 1;
 
+// Devices whose launch facts (occupancy) are cached per process.
+constexpr int kMaxDevices = 64;
+
 // Resident schedule for one-chunk launches of whole stream groups: a wave
 // preloads the states of all its groups before its first store.  The register
 // queue holds up to this many groups: enough for 2^20 streams on the waves the

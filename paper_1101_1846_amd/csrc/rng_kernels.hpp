@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "rng_device.hpp"
 #include "rng_internal.hpp"
 #include "rng_aux_kernels.hpp"
@@ -391,17 +393,23 @@ int launch_generate_shape(const GenArgs &a, hipStream_t stream)
     b.resident = 0;
     if constexpr (kMode == 2) {
         if (a.P == 1 && a.vec4 && a.S % 64 == 0 && a.N % K == 0) {
-            // the workgroups resident at once; each wave then takes at most
+            // the workgroups resident at once on the current device (queried
+            // once per device); each wave then takes at most
             // resident_groups(WG, K) groups
-            static const uint64_t resident = [] {
-                int per_cu = 0, dev = 0, cus = 0;
-                if (hipGetDevice(&dev) != hipSuccess ||
-                    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-                    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_generate<G, DT, WG, U, K, kMode>, WG, 0) !=
-                        hipSuccess)
-                    return (uint64_t)0;
-                return (uint64_t)per_cu * (uint64_t)cus;
-            }();
+            static std::atomic<uint64_t> cache[kMaxDevices];
+            uint64_t resident = 0;
+            int dev = 0;
+            if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices) {
+                resident = cache[dev].load(std::memory_order_relaxed);
+                int per_cu = 0, cus = 0;
+                if (!resident &&
+                    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+                    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_generate<G, DT, WG, U, K, kMode>, WG, 0) ==
+                        hipSuccess) {
+                    resident = (uint64_t)per_cu * (uint64_t)cus;
+                    cache[dev].store(resident, std::memory_order_relaxed);
+                }
+            }
             if (resident && blocks <= resident * resident_groups(WG, K)) {
                 b.resident = 1;
                 if (blocks > resident) blocks = resident;
