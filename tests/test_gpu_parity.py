@@ -256,6 +256,40 @@ def test_fused_pi_parity(rng, torch, oracle, name, S, N):
 PERSIST = [(262464, 192, None), (262464, 64, None), (262464, 96, (1024, 4)), (65600, 128, (64, 16))]
 
 
+# Long rows on the resident schedule: 1025 groups leave most waves fewer
+# groups than the register queue holds; 5, 9 and 36 tiles per row.
+LONG_ROWS = [(65600, 640, (256, 8)), (65600, 1152, None), (65600, 1152, (128, 4)), (65600, 1152, (512, 4))]
+
+
+@pytest.mark.parametrize("name", GENS)
+@pytest.mark.parametrize("dt", ["u32", "f32"])
+@pytest.mark.parametrize("S,N,shape", LONG_ROWS)
+def test_long_rows_parity(rng, torch, oracle, name, dt, S, N, shape):
+    g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
+    t = rng.DTYPES[dt]
+    st = _dev_state(torch, rng, g, 13, S)
+    out = _gen(torch, rng, g, st, S, N, t, shape=shape)
+    ref_st = oracle.seed(o, 13, S)
+    ref = oracle.generate(o, ref_st, N, t, threads=16)
+    assert np.array_equal(out.view(np.uint32), ref.view(np.uint32))
+    assert np.array_equal(_host(st), ref_st)
+
+
+@pytest.mark.parametrize("name", ["MWC32", "XS256", "KISS"])
+def test_long_rows_full_queue(rng, torch, oracle, name):
+    """2^20 streams: every wave holds as many groups as its register queue
+    does, with 12 tiles per row (1536 samples, 6 GiB)."""
+    g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
+    S, N = 1 << 20, 1536
+    st = _dev_state(torch, rng, g, 14, S)
+    out = _gen(torch, rng, g, st, S, N, rng.RNG_U32, shape=(256, 8))
+    ref_st = oracle.seed(o, 14, S)
+    ref = oracle.generate(o, ref_st, N, threads=16)
+    assert np.array_equal(out, ref)
+    assert np.array_equal(_host(st), ref_st)
+    del out, ref
+
+
 @pytest.mark.parametrize("name", GENS)
 @pytest.mark.parametrize("dt", ["u32", "f32"])
 @pytest.mark.parametrize("S,N,shape", PERSIST)
