@@ -238,6 +238,35 @@ static bool mul_overflows(uint64_t a, uint64_t b, uint64_t *r)
     return __builtin_mul_overflow(a, b, r);
 }
 
+// Jump constants of the rotated tile order (d N / 4 samples, d = 0..3).  The
+// xorshift32 columns cost about 12 us of host time per distance, so the last
+// few row lengths are cached.
+static void rot_constants(int g, uint64_t N, GenArgs &a)
+{
+    if (g == RNG_MWC32) {
+        for (int d = 0; d < 4; ++d) a.rot_mwc32[d] = mwc32_fold_const((uint64_t)d * (N / 4));
+        return;
+    }
+    struct Entry {
+        uint64_t N = 0;
+        uint32_t cols[4][32];
+    };
+    static std::mutex mu;
+    static Entry cache[8];
+    static unsigned next = 0;
+    std::lock_guard<std::mutex> lk(mu);
+    for (const Entry &e : cache)
+        if (e.N == N) {
+            std::memcpy(a.rot_xs32, e.cols, sizeof(e.cols));
+            return;
+        }
+    Entry &e = cache[next++ % 8];
+    uint32_t A, C;
+    for (int d = 0; d < 4; ++d) xs32_lcg_jump((uint64_t)d * (N / 4), e.cols[d], &A, &C);
+    e.N = N;
+    std::memcpy(a.rot_xs32, e.cols, sizeof(e.cols));
+}
+
 // Shared by rng_generate and the split path: one generate launch over
 // S streams whose states live at stride ld.
 int generate_impl(int g, int dt, uint32_t *d_state, uint64_t ld, uint64_t S, uint64_t N, void *d_out,
@@ -257,6 +286,11 @@ int generate_impl(int g, int dt, uint32_t *d_state, uint64_t ld, uint64_t S, uin
     a.nt = 0;  // plain stores: the streaming hint measured slower for these writes
     a.tab = tab;
     choose_chunks(g, S, N, kGenTile, &a.C, &a.P);
+    // rows of whole 4 KiB multiples on the resident schedule: rotated tile order
+    if ((g == RNG_MWC32 || g == RNG_XS32) && staged && a.P == 1 && a.vec4 && S % 64 == 0 && N % 1024 == 0) {
+        a.rot = 1;
+        rot_constants(g, N, a);
+    }
     rc = dispatch_generate(g, dt, a, (int)shape.wg, (int)shape.unroll, staged, st);
     if (rc != kStatesNotWritten) return check_launch(rc, "rng_generate");
     // chunks of one stream in several workgroups: the states advance after

@@ -190,6 +190,107 @@ __device__ __forceinline__ void gen_resident(const GenArgs &a, uint32_t *tile, i
     for (int i = 0; i < QPR; ++i) *(u32x4 *)(pdst + (uint64_t)(i * RPI) * N) = P[i];
 }
 
+// Rows that are whole multiples of 4 KiB: with every wave at the same tile
+// index, all concurrent writes share address bits 9-11 and the HBM write
+// rate drops by a sixth.  Wave w therefore starts each of its rows at tile
+// (w mod 4) T / 4: it jumps the state ahead by (w mod 4) N / 4 (one multiply
+// for MWC32, a 32x32 product for XS32, constants from the host), writes to
+// the end of the row, writes the state back, and wraps round to write the
+// first tiles from the original state.
+template <class G>
+__device__ __forceinline__ void rot_jump(G &g, const GenArgs &a, uint32_t d)
+{
+    if constexpr (G::kId == G_MWC32) {
+        const uint64_t z = mwc32_mulmod((uint64_t)g.c << 32 | g.x, a.rot_mwc32[d], a.tab.mwc32_a, a.tab.mwc32_m);
+        g.x = (uint32_t)z;
+        g.c = (uint32_t)(z >> 32);
+    } else {
+        uint32_t r = 0;
+#pragma unroll
+        for (int j = 0; j < 32; ++j) r ^= a.rot_xs32[d][j] & (0u - ((g.y >> j) & 1u));
+        g.y = r;
+    }
+}
+
+template <class G, int DT, int U, int K, int MG>
+__device__ __forceinline__ void gen_resident_rot(const GenArgs &a, uint32_t *tile, int lane, uint64_t wave,
+                                                 uint64_t nwaves)
+{
+    constexpr int LD = K + 4, QPR = K / 4, RPI = 64 / QPR;
+    const int r0 = lane / QPR, q = lane % QPR;
+    const uint32_t *src = tile + r0 * LD + 4 * q;
+    uint32_t *row = tile + lane * LD;
+    const uint64_t N = a.N, groups = a.S / 64;
+    if (wave >= groups) return;
+    const uint32_t ng = (uint32_t)((groups - wave + nwaves - 1) / nwaves);
+    const uint32_t T = (uint32_t)(N / K);
+    const uint32_t d = (uint32_t)(wave & 3), t0 = d * (T / 4);  // first tile of every row of this wave
+    uint32_t *out = (uint32_t *)a.out;
+    G gs[MG];
+#pragma unroll
+    for (int i = 0; i < MG; ++i)
+        if ((uint32_t)i < ng) gs[i].load(a.state, a.ld, (wave + (uint64_t)i * nwaves) * 64 + lane, a.tab);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): every state is in before the first store
+    G g0 = gs[0], g = g0;                // g0: the row's start, kept for the wrap
+    if (d) rot_jump(g, a, d);
+    uint64_t sb = wave;
+    u32x4 P[QPR];
+#pragma unroll
+    for (int k = 0; k < K; k += U) gen_to_row<G, DT, U>(g, row, k);
+    RNGX_COMPILER_FENCE();
+#pragma unroll
+    for (int i = 0; i < QPR; ++i) P[i] = *(const u32x4 *)(src + i * RPI * LD);
+    RNGX_COMPILER_FENCE();
+    uint32_t *pdst = out + (sb * 64 + r0) * N + (uint64_t)t0 * K + 4 * q;
+    uint32_t n = 1;  // tiles of the current row done
+    for (uint32_t gi = 0;;) {
+        for (; n < T; ++n) {
+            uint32_t t = t0 + n;
+            if (t >= T) t -= T;
+            if (t == 0 && n != 0) {  // wrapped: g holds the end-of-row state
+                g.store(a.state, a.ld, sb * 64 + lane);
+                g = g0;
+            }
+#pragma unroll
+            for (int k = 0; k < K; k += U) {
+                gen_to_row<G, DT, U>(g, row, k);
+#pragma unroll
+                for (int i = k * QPR / K; i < (k + U) * QPR / K; ++i)
+                    *(u32x4 *)(pdst + (uint64_t)(i * RPI) * N) = P[i];
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            RNGX_COMPILER_FENCE();
+#pragma unroll
+            for (int i = 0; i < QPR; ++i) P[i] = *(const u32x4 *)(src + i * RPI * LD);
+            RNGX_COMPILER_FENCE();
+            pdst = out + (sb * 64 + r0) * N + (uint64_t)t * K + 4 * q;
+        }
+        if (t0 == 0) g.store(a.state, a.ld, sb * 64 + lane);  // no wrap: g is the end-of-row state
+        if (++gi == ng) break;
+        sb += nwaves;
+#pragma unroll
+        for (int i = 0; i + 1 < MG; ++i) gs[i] = gs[i + 1];
+        g0 = gs[0];
+        g = g0;
+        if (d) rot_jump(g, a, d);
+        n = 0;
+    }
+#pragma unroll
+    for (int i = 0; i < QPR; ++i) *(u32x4 *)(pdst + (uint64_t)(i * RPI) * N) = P[i];
+}
+
+template <class G, int DT, int WG, int U>
+__global__ __launch_bounds__(WG) void k_generate_rot(GenArgs a)
+{
+    constexpr int K = 128, LD = K + 4, NW = WG / 64;
+    __shared__ __attribute__((aligned(16))) uint32_t lds[NW * 64 * LD];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t wave = (uint64_t)blockIdx.x * NW + wv;
+    gen_resident_rot<G, DT, U, K, resident_groups(WG, K)>(a, &lds[wv * 64 * LD], lane, wave,
+                                                          (uint64_t)gridDim.x * NW);
+}
+
 template <class G, int DT, int WG, int U, int K, int kMode>
 __global__ __launch_bounds__(WG) void k_generate(GenArgs a)
 {
@@ -416,7 +517,15 @@ int launch_generate_shape(const GenArgs &a, hipStream_t stream)
             }
         }
     }
-    hipLaunchKernelGGL((k_generate<G, DT, WG, U, K, kMode>), dim3((unsigned)blocks), dim3(WG), 0, stream, b);
+    bool launched = false;
+    if constexpr (kMode == 2 && K == 128 && (G::kId == G_MWC32 || G::kId == G_XS32)) {
+        if (b.resident && a.rot) {
+            hipLaunchKernelGGL((k_generate_rot<G, DT, WG, U>), dim3((unsigned)blocks), dim3(WG), 0, stream, b);
+            launched = true;
+        }
+    }
+    if (!launched)
+        hipLaunchKernelGGL((k_generate<G, DT, WG, U, K, kMode>), dim3((unsigned)blocks), dim3(WG), 0, stream, b);
     if (hipGetLastError() != hipSuccess) return -1;
     return a.P > 1 && !chunks_in_workgroup(a.P, WG / 64) ? kStatesNotWritten : 0;
 }

@@ -275,6 +275,42 @@ def test_long_rows_parity(rng, torch, oracle, name, dt, S, N, shape):
     assert np.array_equal(_host(st), ref_st)
 
 
+# Rows of whole 4 KiB multiples: MWC32 and XS32 start every row of wave w at
+# tile (w mod 4) T / 4 by jump-ahead and wrap round (the other generators
+# keep the plain order).
+ROT_ROWS = [(65600, 1024, None), (65600, 2048, (128, 4)), (65600, 1024, (64, 16)), (65536, 3072, (256, 8))]
+
+
+@pytest.mark.parametrize("name", GENS)
+@pytest.mark.parametrize("dt", ["u32", "f32"])
+@pytest.mark.parametrize("S,N,shape", ROT_ROWS)
+def test_rotated_rows_parity(rng, torch, oracle, name, dt, S, N, shape):
+    g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
+    t = rng.DTYPES[dt]
+    st = _dev_state(torch, rng, g, 15, S)
+    out = _gen(torch, rng, g, st, S, N, t, shape=shape)
+    ref_st = oracle.seed(o, 15, S)
+    ref = oracle.generate(o, ref_st, N, t, threads=16)
+    assert np.array_equal(out.view(np.uint32), ref.view(np.uint32))
+    assert np.array_equal(_host(st), ref_st)
+
+
+@pytest.mark.parametrize("name", ["MWC32", "XS32"])
+def test_rotated_rows_full_queue(rng, torch, oracle, name):
+    """2^20 streams x 1024 with a full register queue per wave, twice in a row
+    (the written-back states must continue the rows)."""
+    g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
+    S, N = 1 << 20, 1024
+    st = _dev_state(torch, rng, g, 16, S)
+    ref_st = oracle.seed(o, 16, S)
+    for _ in range(2):
+        out = _gen(torch, rng, g, st, S, N, rng.RNG_U32, shape=(256, 4))
+        ref = oracle.generate(o, ref_st, N, threads=16)
+        assert np.array_equal(out, ref)
+        del out, ref
+    assert np.array_equal(_host(st), ref_st)
+
+
 @pytest.mark.parametrize("name", ["MWC32", "XS256", "KISS"])
 def test_long_rows_full_queue(rng, torch, oracle, name):
     """2^20 streams: every wave holds as many groups as its register queue
