@@ -3,6 +3,7 @@
 // multi-kernel operations (sequence splitting).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -285,6 +286,14 @@ int generate_impl(int g, int dt, uint32_t *d_state, uint64_t ld, uint64_t S, uin
     a.vec4 = (N % 4 == 0) && (((uintptr_t)d_out & 15) == 0);
     a.nt = 0;  // plain stores: the streaming hint measured slower for these writes
     a.tab = tab;
+    if (staged && S < 64) {
+        // fewer streams than lanes: one lane per chunk, about 2^17 lanes
+        const uint64_t p = ((uint64_t)1 << 17) / S;
+        uint64_t c = std::max<uint64_t>(min_chunk(g), (N + p - 1) / p);
+        c = (c + 63) / 64 * 64;
+        const uint64_t P = (N + c - 1) / c;
+        if (P > 1) return check_launch(generate_few(g, dt, d_state, ld, S, N, c, P, d_out, tab, st), "rng_generate");
+    }
     choose_chunks(g, S, N, kGenTile, &a.C, &a.P);
     // rows of whole 4 KiB multiples on the resident schedule: rotated tile order
     if ((g == RNG_MWC32 || g == RNG_XS32) && staged && a.P == 1 && a.vec4 && S % 64 == 0 && N % 1024 == 0) {

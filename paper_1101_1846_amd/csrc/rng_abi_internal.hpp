@@ -34,6 +34,11 @@ int dispatch_tree_level(int g, uint32_t *ws, uint64_t T, uint32_t shift, uint64_
 int dispatch_state_copy(int g, const uint32_t *src, uint64_t ss, uint64_t si, uint32_t *dst, uint64_t ds,
                         uint64_t di, hipStream_t s);
 
+// Fewer streams than a wave has lanes: lane v takes chunk v mod P of stream
+// v / P (chunks of C samples), then the states advance by N (few.hip).
+int generate_few(int g, int dt, uint32_t *d_state, uint64_t ld, uint64_t S, uint64_t N, uint64_t C, uint64_t P,
+                 void *d_out, const DevTables &tab, hipStream_t st);
+
 // rng_batch_set without the check that no two requests share a state (for
 // callers that keep one request per state).
 int batch_set_distinct(rng_batch_t *h, const rng_request_t *reqs, uint32_t n);

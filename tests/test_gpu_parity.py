@@ -136,6 +136,27 @@ def test_chunked_resume_equals_one_call(rng, torch, oracle, name, shape):
     assert np.array_equal(_host(a), ref_st)
 
 
+FEW = [(1, (1 << 20) + 13), (2, 70001), (5, 1 << 16), (63, 12345)]
+
+
+@pytest.mark.parametrize("name", GENS)
+@pytest.mark.parametrize("dt", ["u32", "f32"])
+@pytest.mark.parametrize("S,N", FEW)
+def test_few_streams_one_lane_per_chunk(rng, torch, oracle, name, dt, S, N):
+    """Fewer streams than a wave has lanes: every lane takes one chunk of one
+    stream (ragged last chunks), the output is 4-byte but not 16-byte aligned
+    on the second call, and the states come back advanced by N each time."""
+    g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
+    t = rng.DTYPES[dt]
+    st = _dev_state(torch, rng, g, 17, S)
+    ref_st = oracle.seed(o, 17, S)
+    for off in (0, 1, 0):
+        out = _gen(torch, rng, g, st, S, N, t, offset_words=off)
+        ref = oracle.generate(o, ref_st, N, t, threads=4)
+        assert np.array_equal(out.view(np.uint32), ref.view(np.uint32)), off
+    assert np.array_equal(_host(st), ref_st)
+
+
 @pytest.mark.parametrize("name", GENS)
 def test_run_twice_identical(rng, torch, name):
     g = rng.GENERATORS[name]
