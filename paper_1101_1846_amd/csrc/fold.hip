@@ -95,7 +95,7 @@ extern "C" int rng_generate_fold(int g, uint32_t *d_state, uint64_t n_streams, u
     a.N = n;
     a.fold = d_fold;
     a.tab = tab;
-    choose_chunks(g, n_streams, n, 8, &a.C, &a.P);
+    choose_chunks(g, n_streams, n, 8, &a.C, &a.P, (uint64_t)1 << 17);
     hipStream_t st = (hipStream_t)stream;
     int rc = -2;
     switch (g) {
