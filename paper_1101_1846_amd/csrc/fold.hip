@@ -19,8 +19,9 @@ namespace {
 struct FoldArgs {
     uint32_t *state;
     uint64_t ld, S, N;
-    uint64_t C;  // chunk length
-    uint32_t P;  // chunks per stream
+    uint64_t C;      // chunk length
+    uint32_t P;      // chunks per stream
+    uint32_t lanes;  // fewer streams than lanes: lane v takes chunk v mod P of stream v / P
     uint32_t *fold;
     DevTables tab;
 };
@@ -37,17 +38,29 @@ __global__ __launch_bounds__(256) void k_fold(FoldArgs a)
 {
     const int lane = threadIdx.x & 63;
     const uint64_t wave = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const uint64_t sb = wave / a.P, j = wave - sb * a.P;
-    const uint64_t s0 = sb * 64;
-    if (s0 >= a.S) return;
-    const uint64_t kb = j * a.C;
-    if (kb >= a.N) return;
-    const uint64_t ke = min(kb + a.C, a.N);
-    const bool valid = s0 + lane < a.S;
-    const uint64_t s = valid ? s0 + lane : s0;
+    uint64_t s, kb, ke;
+    bool valid;
+    if (a.lanes) {
+        // one chunk per lane: its own stream, start and (per-lane) jump
+        const uint64_t total = a.S * a.P, v = wave * 64 + lane;
+        if (wave * 64 >= total) return;  // whole waves
+        valid = v < total;
+        s = valid ? v / a.P : 0;
+        kb = valid ? (v - s * a.P) * a.C : 0;
+        ke = valid ? min(kb + a.C, a.N) : 0;
+    } else {
+        const uint64_t sb = wave / a.P, j = wave - sb * a.P;
+        const uint64_t s0 = sb * 64;
+        if (s0 >= a.S) return;
+        kb = j * a.C;
+        if (kb >= a.N) return;
+        ke = min(kb + a.C, a.N);
+        valid = s0 + lane < a.S;
+        s = valid ? s0 + lane : s0;
+    }
     G g;
     g.load(a.state, a.ld, s, a.tab);
-    if (j) g.jump(kb, a.tab);
+    if (kb) g.jump(kb, a.tab);
     uint32_t acc = 0;
     uint64_t k = kb;
     for (; k + U <= ke; k += U) {
@@ -55,6 +68,25 @@ __global__ __launch_bounds__(256) void k_fold(FoldArgs a)
         for (int u = 0; u < U; ++u) acc ^= fold_bits<DT>(g.next());
     }
     for (; k < ke; ++k) acc ^= fold_bits<DT>(g.next());
+    if (a.lanes) {
+        // Many lanes hold chunks of one stream: XOR them within the wave first
+        // (the streams of the first and the last lane), so that a wave issues
+        // at most two atomics there instead of 64 on one word.
+        const uint32_t sl = (uint32_t)s;
+        const uint32_t s_first = __shfl(sl, 0, 64), s_last = __shfl(sl, 63, 64);
+        const bool valid_last = __shfl((int)valid, 63, 64) != 0;
+        uint32_t x0 = valid && sl == s_first ? acc : 0u;
+        uint32_t x1 = valid && sl == s_last && sl != s_first ? acc : 0u;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            x0 ^= (uint32_t)__shfl_xor((int)x0, off, 64);
+            x1 ^= (uint32_t)__shfl_xor((int)x1, off, 64);
+        }
+        if (lane == 0) atomicXor(&a.fold[s_first], x0);
+        if (lane == 63 && valid_last && s_last != s_first) atomicXor(&a.fold[s_last], x1);
+        if (valid && sl != s_first && sl != s_last) atomicXor(&a.fold[s], acc);  // streams between them
+        return;  // P > 1: the host skips the states by N
+    }
     if (!valid) return;
     if (a.P == 1) a.fold[s] ^= acc;
     else atomicXor(&a.fold[s], acc);
@@ -64,7 +96,7 @@ __global__ __launch_bounds__(256) void k_fold(FoldArgs a)
 template <class G>
 int launch_fold(int dt, const FoldArgs &a, hipStream_t st)
 {
-    const uint64_t waves = ((a.S + 63) / 64) * a.P;
+    const uint64_t waves = a.lanes ? (a.S * a.P + 63) / 64 : ((a.S + 63) / 64) * a.P;
     const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
     if (dt == RNG_F32) hipLaunchKernelGGL((k_fold<G, RNG_DT_F32, 8>), grid, block, 0, st, a);
     else hipLaunchKernelGGL((k_fold<G, RNG_DT_U32, 8>), grid, block, 0, st, a);
@@ -95,7 +127,13 @@ extern "C" int rng_generate_fold(int g, uint32_t *d_state, uint64_t n_streams, u
     a.N = n;
     a.fold = d_fold;
     a.tab = tab;
-    choose_chunks(g, n_streams, n, 8, &a.C, &a.P, (uint64_t)1 << 17);
+    if (n_streams < 64) {
+        lane_chunks(g, n_streams, n, &a.C, &a.P);
+        a.lanes = a.P > 1;
+        if (a.P == 1) a.C = n;
+    } else {
+        choose_chunks(g, n_streams, n, 8, &a.C, &a.P, (uint64_t)1 << 17);
+    }
     hipStream_t st = (hipStream_t)stream;
     int rc = -2;
     switch (g) {

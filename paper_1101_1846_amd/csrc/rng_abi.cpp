@@ -165,6 +165,17 @@ static uint64_t min_chunk(int g)
 
 // Split each stream into P chunks when there are too few streams to fill the
 // chip (256 CUs x 4 SIMDs; aim for >= 2 waves per SIMD).
+// Fewer streams than a wave has lanes: one lane per chunk, about 2^17 lanes,
+// chunks a multiple of 64 samples and at least the generator's minimum.
+void lane_chunks(int g, uint64_t S, uint64_t N, uint64_t *C, uint32_t *P)
+{
+    const uint64_t p = ((uint64_t)1 << 17) / S;
+    uint64_t c = std::max<uint64_t>(min_chunk(g), (N + p - 1) / p);
+    c = (c + 63) / 64 * 64;
+    *C = c;
+    *P = (uint32_t)((N + c - 1) / c);
+}
+
 // Lanes that chunked bulk generation aims for: the waves the device holds at
 // once with 128-deep LDS tiles (4 per CU, 256 CUs) times 64.  Measured
 // against 2^17 and 2^15 over 64..65536 streams: 2^16 is 15-40 % faster than
@@ -292,11 +303,9 @@ int generate_impl(int g, int dt, uint32_t *d_state, uint64_t ld, uint64_t S, uin
     a.nt = 0;  // plain stores: the streaming hint measured slower for these writes
     a.tab = tab;
     if (staged && S < 64) {
-        // fewer streams than lanes: one lane per chunk, about 2^17 lanes
-        const uint64_t p = ((uint64_t)1 << 17) / S;
-        uint64_t c = std::max<uint64_t>(min_chunk(g), (N + p - 1) / p);
-        c = (c + 63) / 64 * 64;
-        const uint64_t P = (N + c - 1) / c;
+        uint64_t c;
+        uint32_t P;
+        lane_chunks(g, S, N, &c, &P);
         if (P > 1) return check_launch(generate_few(g, dt, d_state, ld, S, N, c, P, d_out, tab, st), "rng_generate");
     }
     choose_chunks(g, S, N, kGenTile, &a.C, &a.P, kGenLanes);
@@ -519,7 +528,12 @@ int rng_fused_pi(int g, uint32_t *d_state, uint64_t n_streams, uint64_t n, uint6
     a.N = n;
     a.count = d_count;
     a.tab = tab;
-    choose_chunks(g, n_streams, n, 8, &a.C, &a.P, (uint64_t)1 << 17);
+    if (n_streams < 64) {
+        lane_chunks(g, n_streams, n, &a.C, &a.P);
+        a.lanes = a.P > 1;
+    } else {
+        choose_chunks(g, n_streams, n, 8, &a.C, &a.P, (uint64_t)1 << 17);
+    }
     if (a.P == 1) a.C = n;
     if (int rc = check_launch(dispatch_fused(g, a, (hipStream_t)stream), "rng_fused_pi")) return rc;
     if (a.P == 1) return RNG_OK;

@@ -25,6 +25,8 @@ void set_tuned_shape(int g, int dt, Shape s);
 // Chunks per stream: the largest power of two p with S p <= target_lanes and
 // chunks of at least the generator's minimum length.
 void choose_chunks(int g, uint64_t S, uint64_t N, uint64_t align, uint64_t *C, uint32_t *P, uint64_t target_lanes);
+// Chunks for one lane per chunk (fewer streams than a wave has lanes).
+void lane_chunks(int g, uint64_t S, uint64_t N, uint64_t *C, uint32_t *P);
 int generate_impl(int g, int dt, uint32_t *d_state, uint64_t ld, uint64_t S, uint64_t N, void *d_out,
                   Shape shape, bool staged, hipStream_t st);
 int dispatch_generate(int g, int dt, const GenArgs &a, int wg, int unroll, bool staged, hipStream_t st);

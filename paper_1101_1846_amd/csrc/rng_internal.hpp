@@ -67,6 +67,7 @@ struct FusedArgs {
     uint64_t S, N;
     uint64_t C;  // even chunk length
     uint32_t P;
+    uint32_t lanes;  // fewer streams than lanes: lane v takes chunk v mod P of stream v / P
     uint64_t *count;
     DevTables tab;
 };

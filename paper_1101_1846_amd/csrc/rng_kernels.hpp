@@ -434,19 +434,31 @@ __global__ __launch_bounds__(WG) void k_fused_pi(FusedArgs a)
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t wave = (uint64_t)blockIdx.x * NW + wv;
-    const uint64_t sb = wave / a.P, j = wave - sb * a.P;
-    const uint64_t s0 = sb * 64;
-    if (s0 >= a.S) return;
-    const uint64_t kb = j * a.C;
-    if (kb >= a.N) return;
-    const uint64_t ke = min(kb + a.C, a.N);
-    const uint32_t rows = (uint32_t)min<uint64_t>(64, a.S - s0);
-    const bool valid = (uint32_t)lane < rows;
-    const uint64_t s = valid ? s0 + lane : s0;
+    uint64_t s, kb, ke;
+    bool valid;
+    if (a.lanes) {
+        // one chunk per lane: its own stream, start and (per-lane) jump
+        const uint64_t total_chunks = a.S * a.P, v = wave * 64 + lane;
+        if (wave * 64 >= total_chunks) return;  // whole waves
+        valid = v < total_chunks;
+        s = valid ? v / a.P : 0;
+        kb = valid ? (v - s * a.P) * a.C : 0;
+        ke = valid ? min(kb + a.C, a.N) : 0;
+    } else {
+        const uint64_t sb = wave / a.P, j = wave - sb * a.P;
+        const uint64_t s0 = sb * 64;
+        if (s0 >= a.S) return;
+        kb = j * a.C;
+        if (kb >= a.N) return;
+        ke = min(kb + a.C, a.N);
+        const uint32_t rows = (uint32_t)min<uint64_t>(64, a.S - s0);
+        valid = (uint32_t)lane < rows;
+        s = valid ? s0 + lane : s0;
+    }
 
     G g;
     g.load(a.state, a.ld, s, a.tab);
-    if (j) g.jump(kb, a.tab);
+    if (kb) g.jump(kb, a.tab);
 
     const uint64_t n = ke - kb;
     const uint64_t full = n / U;
@@ -568,8 +580,8 @@ template <class G>
 int launch_fused_pi_t(const FusedArgs &a, hipStream_t stream)
 {
     constexpr int WG = 256;
-    uint64_t waves = ((a.S + 63) / 64) * a.P;
-    uint64_t blocks = (waves + WG / 64 - 1) / (WG / 64);
+    const uint64_t waves = a.lanes ? (a.S * a.P + 63) / 64 : ((a.S + 63) / 64) * a.P;
+    const uint64_t blocks = (waves + WG / 64 - 1) / (WG / 64);
     hipLaunchKernelGGL((k_fused_pi<G, WG, 8>), dim3((unsigned)blocks), dim3(WG), 0, stream, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

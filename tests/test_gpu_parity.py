@@ -257,7 +257,7 @@ def test_leapfrog_arguments(rng, torch):
 
 
 @pytest.mark.parametrize("name", ["KISS", "XS256", "MWC32"])
-@pytest.mark.parametrize("S,N", [(1, 2), (1000, 64), (333, 65), (64, 1000), (2, 40000)])
+@pytest.mark.parametrize("S,N", [(1, 2), (1000, 64), (333, 65), (64, 1000), (2, 40000), (1, (1 << 20) + 3)])
 def test_fused_pi_parity(rng, torch, oracle, name, S, N):
     g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
     st = _dev_state(torch, rng, g, 6, S)
@@ -363,7 +363,7 @@ def test_large_grid_parity(rng, torch, oracle, name, dt, S, N, shape):
 
 @pytest.mark.parametrize("name", GENS)
 @pytest.mark.parametrize("dt", ["u32", "f32"])
-@pytest.mark.parametrize("S,N", [(1, 1), (1000, 77), (64, 4096), (3, 100000), (70000, 16)])
+@pytest.mark.parametrize("S,N", [(1, 1), (1000, 77), (64, 4096), (3, 100000), (70000, 16), (1, (1 << 20) + 3)])
 def test_fold_parity(rng, torch, oracle, name, dt, S, N):
     """Without write-back: the per-stream XOR of the n outputs (chunked with jumps
     for few streams) and the final states equal the oracle's."""
