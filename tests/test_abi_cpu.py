@@ -89,6 +89,25 @@ def test_argument_validation(rng):
     assert "generator" in rng.rng_last_error() or rng.rng_last_error()
 
 
+def test_fold_and_leapfrog_validation(rng):
+    L = rng.raw()
+    fake = 0x10000
+    assert L.rng_generate_fold(99, fake, 4, 4, 0, fake, None) == rng.RNG_EINVAL
+    assert L.rng_generate_fold(rng.RNG_XS32, fake, 4, 4, 9, fake, None) == rng.RNG_EINVAL
+    assert L.rng_generate_fold(rng.RNG_XS32, None, 4, 4, 0, fake, None) == rng.RNG_EINVAL
+    assert L.rng_generate_fold(rng.RNG_XS32, fake, 4, 4, 0, fake + 2, None) == rng.RNG_EINVAL
+    assert L.rng_generate_fold(rng.RNG_XS32, None, 4, 0, 0, None, None) == rng.RNG_OK
+    for name, g in rng.GENERATORS.items():
+        need = rng.rng_leapfrog_workspace_bytes(g, 1 << 10)
+        assert need >= (1 << 10) * 4 * rng.rng_state_words(g)
+        assert L.rng_generate_leapfrog(g, fake, 1 << 20, 1 << 10, 0, fake, fake, fake, need - 256, None) \
+            == rng.RNG_ENOMEM, name
+    assert L.rng_generate_leapfrog(rng.RNG_MWC32, fake, 100, 0, 0, fake, fake, fake, 1 << 20, None) \
+        == rng.RNG_EINVAL
+    assert L.rng_generate_leapfrog(rng.RNG_MWC32, fake, 100, 4, 0, fake, fake, fake + 16, 1 << 20, None) \
+        == rng.RNG_EINVAL  # workspace must be 256-byte aligned
+
+
 def test_shape_roundtrip(rng):
     g, t = rng.RNG_XS32, rng.RNG_F32
     old = rng.rng_get_shape(g, t)
