@@ -257,31 +257,35 @@ static bool mul_overflows(uint64_t a, uint64_t b, uint64_t *r)
 
 // Jump constants of the rotated tile order (d N / 4 samples, d = 0..3).  The
 // xorshift32 columns cost about 12 us of host time per distance, so the last
-// few row lengths are cached.
+// few row lengths are cached.  MWC1616 needs none from the host: the MWC16
+// words' constants depend on the stream's multiplier and are built in LDS.
 static void rot_constants(int g, uint64_t N, GenArgs &a)
 {
     if (g == RNG_MWC32) {
         for (int d = 0; d < 4; ++d) a.rot_mwc32[d] = mwc32_fold_const((uint64_t)d * (N / 4));
         return;
     }
+    if (g == RNG_MWC1616) return;
     struct Entry {
         uint64_t N = 0;
         uint32_t cols[4][32];
+        uint32_t lcg[4][2];
     };
     static std::mutex mu;
     static Entry cache[8];
     static unsigned next = 0;
     std::lock_guard<std::mutex> lk(mu);
+    const Entry *hit = nullptr;
     for (const Entry &e : cache)
-        if (e.N == N) {
-            std::memcpy(a.rot_xs32, e.cols, sizeof(e.cols));
-            return;
-        }
-    Entry &e = cache[next++ % 8];
-    uint32_t A, C;
-    for (int d = 0; d < 4; ++d) xs32_lcg_jump((uint64_t)d * (N / 4), e.cols[d], &A, &C);
-    e.N = N;
-    std::memcpy(a.rot_xs32, e.cols, sizeof(e.cols));
+        if (e.N == N) hit = &e;
+    if (!hit) {
+        Entry &e = cache[next++ % 8];
+        for (int d = 0; d < 4; ++d) xs32_lcg_jump((uint64_t)d * (N / 4), e.cols[d], &e.lcg[d][0], &e.lcg[d][1]);
+        e.N = N;
+        hit = &e;
+    }
+    std::memcpy(a.rot_xs32, hit->cols, sizeof(hit->cols));
+    std::memcpy(a.rot_lcg, hit->lcg, sizeof(hit->lcg));
 }
 
 // Shared by rng_generate and the split path: one generate launch over
@@ -310,7 +314,7 @@ int generate_impl(int g, int dt, uint32_t *d_state, uint64_t ld, uint64_t S, uin
     }
     choose_chunks(g, S, N, kGenTile, &a.C, &a.P, kGenLanes);
     // rows of whole 4 KiB multiples on the resident schedule: rotated tile order
-    if ((g == RNG_MWC32 || g == RNG_XS32) && staged && a.P == 1 && a.vec4 && S % 64 == 0 && N % 1024 == 0) {
+    if (g != RNG_XS256 && staged && a.P == 1 && a.vec4 && S % 64 == 0 && N % 1024 == 0) {
         a.rot = 1;
         rot_constants(g, N, a);
     }

@@ -55,10 +55,11 @@ struct GenArgs {
     uint32_t vec4;    // rows 16-byte aligned: 128-bit stores
     uint32_t nt;      // non-temporal store hint
     uint32_t resident; // waves stride over 64-stream groups with preloaded states (set by the launcher)
-    uint32_t rot;      // MWC32 / XS32 rows of whole 4 KiB multiples: rotated tile order (constants below)
+    uint32_t rot;      // rows of whole 4 KiB multiples (all but XS256): rotated tile order (constants below)
     DevTables tab;
     uint64_t rot_mwc32[4];     // a^(d N / 4) * 2^64 mod m, d = 0..3
-    uint32_t rot_xs32[4][32];  // columns of the xorshift32 M^(d N / 4)
+    uint32_t rot_xs32[4][32];  // columns of the xorshift32 M^(d N / 4) (XS32, KISS)
+    uint32_t rot_lcg[4][2];    // A, C of d N / 4 LCG steps (KISS); the MWC16 words' constants are built in LDS
 };
 
 struct FusedArgs {

@@ -193,28 +193,50 @@ __device__ __forceinline__ void gen_resident(const GenArgs &a, uint32_t *tile, i
 // Rows that are whole multiples of 4 KiB: with every wave at the same tile
 // index, all concurrent writes share address bits 9-11 and the HBM write
 // rate drops by a sixth.  Wave w therefore starts each of its rows at tile
-// (w mod 4) T / 4: it jumps the state ahead by (w mod 4) N / 4 (one multiply
-// for MWC32, a 32x32 product for XS32, constants from the host), writes to
-// the end of the row, writes the state back, and wraps round to write the
-// first tiles from the original state.
+// (w mod 4) T / 4: it jumps the state ahead by d N / 4 with d = w mod 4,
+// writes to the end of the row, writes the state back, and wraps round to
+// write the first tiles from the original state.  The jump is one product
+// per word with constants that every stream of the launch shares: a^(d N/4)
+// for MWC32, the columns of the xorshift32 M^(d N/4) and the LCG's A, C from
+// the host; for the MWC16 words, whose multiplier varies by stream,
+// a_i^(d N/4) for all 392 multipliers, built by each workgroup in LDS.
+// XS256 (a 256 x 256 product per row) keeps the plain order.
+struct RotMwc16 {
+    const uint16_t *t392;  // LDS: the ascending multipliers
+    const uint32_t *c16;   // LDS: [3][392], a_i^(d N / 4) * 2^48 mod m_i for d = 1..3
+};
+
+__device__ __forceinline__ uint32_t rot_xs32(const uint32_t *cols, uint32_t y)
+{
+    uint32_t r = 0;
+#pragma unroll
+    for (int j = 0; j < 32; ++j) r ^= cols[j] & (0u - ((y >> j) & 1u));
+    return r;
+}
+
 template <class G>
-__device__ __forceinline__ void rot_jump(G &g, const GenArgs &a, uint32_t d)
+__device__ __forceinline__ void rot_jump(G &g, const GenArgs &a, uint32_t d, const RotMwc16 &r)
 {
     if constexpr (G::kId == G_MWC32) {
         const uint64_t z = mwc32_mulmod((uint64_t)g.c << 32 | g.x, a.rot_mwc32[d], a.tab.mwc32_a, a.tab.mwc32_m);
         g.x = (uint32_t)z;
         g.c = (uint32_t)(z >> 32);
-    } else {
-        uint32_t r = 0;
-#pragma unroll
-        for (int j = 0; j < 32; ++j) r ^= a.rot_xs32[d][j] & (0u - ((g.y >> j) & 1u));
-        g.y = r;
+    } else if constexpr (G::kId == G_XS32) {
+        g.y = rot_xs32(a.rot_xs32[d], g.y);
+    } else {  // MWC1616, KISS
+        const uint32_t *c = r.c16 + (d - 1) * 392;
+        g.z = mwc16_mulmod(g.z, c[t392_index(r.t392, g.a1)], g.a1);
+        g.w = mwc16_mulmod(g.w, c[t392_index(r.t392, g.a2)], g.a2);
+        if constexpr (G::kId == G_KISS) {
+            g.jsr = rot_xs32(a.rot_xs32[d], g.jsr);
+            g.jcong = a.rot_lcg[d][0] * g.jcong + a.rot_lcg[d][1];
+        }
     }
 }
 
 template <class G, int DT, int U, int K, int MG>
 __device__ __forceinline__ void gen_resident_rot(const GenArgs &a, uint32_t *tile, int lane, uint64_t wave,
-                                                 uint64_t nwaves)
+                                                 uint64_t nwaves, const RotMwc16 &rt)
 {
     constexpr int LD = K + 4, QPR = K / 4, RPI = 64 / QPR;
     const int r0 = lane / QPR, q = lane % QPR;
@@ -232,7 +254,7 @@ __device__ __forceinline__ void gen_resident_rot(const GenArgs &a, uint32_t *til
         if ((uint32_t)i < ng) gs[i].load(a.state, a.ld, (wave + (uint64_t)i * nwaves) * 64 + lane, a.tab);
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): every state is in before the first store
     G g0 = gs[0], g = g0;                // g0: the row's start, kept for the wrap
-    if (d) rot_jump(g, a, d);
+    if (d) rot_jump(g, a, d, rt);
     uint64_t sb = wave;
     u32x4 P[QPR];
 #pragma unroll
@@ -272,7 +294,7 @@ __device__ __forceinline__ void gen_resident_rot(const GenArgs &a, uint32_t *til
         for (int i = 0; i + 1 < MG; ++i) gs[i] = gs[i + 1];
         g0 = gs[0];
         g = g0;
-        if (d) rot_jump(g, a, d);
+        if (d) rot_jump(g, a, d, rt);
         n = 0;
     }
 #pragma unroll
@@ -283,12 +305,33 @@ template <class G, int DT, int WG, int U>
 __global__ __launch_bounds__(WG) void k_generate_rot(GenArgs a)
 {
     constexpr int K = 128, LD = K + 4, NW = WG / 64;
+    constexpr bool kMwc16 = G::kId == G_MWC1616 || G::kId == G_KISS;
     __shared__ __attribute__((aligned(16))) uint32_t lds[NW * 64 * LD];
+    __shared__ uint16_t s_t392[kMwc16 ? 392 : 1];
+    __shared__ uint32_t s_c16[kMwc16 ? 3 * 392 : 1];
+    if constexpr (kMwc16) {
+        // a_i^q, a_i^2q, a_i^3q (q = N / 4) in the fold domain of m_i: the
+        // bits of q over the table of a_i^(2^b), then two products
+        const uint64_t q = a.N / 4;
+        for (uint32_t i = threadIdx.x; i < 392u; i += WG) {
+            const uint32_t ai = a.tab.t392[i];
+            const uint32_t *p = a.tab.mwc16_pow + (size_t)i * 64;
+            uint32_t c = (uint32_t)(((uint64_t)1 << 48) % (ai * 65536u - 1u));  // fold image of 1
+            for (int b = 0; b < 64 && (q >> b); ++b)
+                if ((q >> b) & 1) c = mwc16_mulmod(c, p[b], ai);
+            const uint32_t c2 = mwc16_mulmod(c, c, ai);
+            s_t392[i] = (uint16_t)ai;
+            s_c16[i] = c;
+            s_c16[392 + i] = c2;
+            s_c16[784 + i] = mwc16_mulmod(c2, c, ai);
+        }
+        __syncthreads();  // before any wave returns
+    }
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t wave = (uint64_t)blockIdx.x * NW + wv;
     gen_resident_rot<G, DT, U, K, resident_groups(WG, K)>(a, &lds[wv * 64 * LD], lane, wave,
-                                                          (uint64_t)gridDim.x * NW);
+                                                          (uint64_t)gridDim.x * NW, RotMwc16{s_t392, s_c16});
 }
 
 template <class G, int DT, int WG, int U, int K, int kMode>
@@ -530,7 +573,7 @@ int launch_generate_shape(const GenArgs &a, hipStream_t stream)
         }
     }
     bool launched = false;
-    if constexpr (kMode == 2 && K == 128 && (G::kId == G_MWC32 || G::kId == G_XS32)) {
+    if constexpr (kMode == 2 && K == 128 && G::kId != G_XS256) {
         if (b.resident && a.rot) {
             hipLaunchKernelGGL((k_generate_rot<G, DT, WG, U>), dim3((unsigned)blocks), dim3(WG), 0, stream, b);
             launched = true;

@@ -316,7 +316,7 @@ def test_rotated_rows_parity(rng, torch, oracle, name, dt, S, N, shape):
     assert np.array_equal(_host(st), ref_st)
 
 
-@pytest.mark.parametrize("name", ["MWC32", "XS32"])
+@pytest.mark.parametrize("name", ["MWC32", "XS32", "KISS", "MWC1616"])
 def test_rotated_rows_full_queue(rng, torch, oracle, name):
     """2^20 streams x 1024 with a full register queue per wave, twice in a row
     (the written-back states must continue the rows)."""
