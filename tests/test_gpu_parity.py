@@ -202,10 +202,12 @@ def test_skip_many_states(rng, torch, oracle, name, k):
 
 @pytest.mark.parametrize("name", GENS)
 @pytest.mark.parametrize("total,threads", [(1, 1), (1000, 1), (1000, 7), (4096 * 7 + 3, 64), (100000, 1000),
-                                          (65536, 65536), (5, 8)])
+                                          (65536, 65536), (5, 8), (1024 * 192 + 900, 193)])
 def test_split_parity(rng, torch, oracle, name, total, threads):
     """Sequence splitting (Sec. II.A.4): the concatenated thread outputs equal the
-    serial sequence of the one logical stream, and the final state matches."""
+    serial sequence of the one logical stream, and the final state matches.
+    1024 * 192 + 900 over 193 threads: 192 full rows of 1024 (whole 4 KiB rows,
+    the rotated tile order where the generator has one) and a 900-sample tail."""
     g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
     st1 = _dev_state(torch, rng, g, 2, 1)
     ws_bytes = rng.rng_split_workspace_bytes(g, threads)
@@ -316,7 +318,7 @@ def test_rotated_rows_parity(rng, torch, oracle, name, dt, S, N, shape):
     assert np.array_equal(_host(st), ref_st)
 
 
-@pytest.mark.parametrize("name", ["MWC32", "XS32", "KISS", "MWC1616"])
+@pytest.mark.parametrize("name", GENS)
 def test_rotated_rows_full_queue(rng, torch, oracle, name):
     """2^20 streams x 1024 with a full register queue per wave, twice in a row
     (the written-back states must continue the rows)."""
