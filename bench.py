@@ -28,7 +28,7 @@ HBM_PEAK_GBPS = 8000.0           # MI355X HBM3E, 8 TB/s
 # FMA as 2 operations, so 78.6e12 lane-operations/s (256 CUs x 2.4 GHz x 128).
 VALU_PEAK_OPS = 157.3e12 / 2
 FUSED_OPS_PER_SAMPLE = 24
-FUSED_VALU_PER_SAMPLE = 21.5     # 172 VALU instructions per 8 samples in the compiled loop
+FUSED_VALU_PER_SAMPLE = 19.5     # 156 VALU instructions per 8 samples in the compiled loop
 
 S_BULK, N_BULK = 1 << 20, 256
 STEP_GENS = ["XS256", "XS32", "KISS"]

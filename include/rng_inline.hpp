@@ -43,11 +43,15 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
 }
 
 // One base-2^16 MWC word z = c * 2^16 + x: z <- a * (z & 0xFFFF) + (z >> 16)
-// (eq. (2)-(3) with the mask and shift of Sec. II.A.1).  Both factors are
-// below 2^16, so the 24-bit multiply(-add) is exact.
+// (eq. (2)-(3) with the mask and shift of Sec. II.A.1).  v_mad_u32_u16 reads
+// only the low 16 bits of both factors, so the mask costs no instruction: a
+// shift and one multiply-add per word (for the same expression in C the
+// compiler emits an AND and a 24-bit multiply-add).
 __device__ __forceinline__ uint32_t mwc16_step(uint32_t z, uint32_t a)
 {
-    return __umul24(a, z & 0xFFFFu) + (z >> 16);
+    uint32_t r;
+    asm("v_mad_u32_u16 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(z), "v"(z >> 16));
+    return r;
 }
 }  // namespace detail
 
