@@ -148,6 +148,8 @@ def main():
 
     # ------------------------------------------------- measured write ceiling
     ceil = write_ceiling(torch, dev)
+    shapes = [R.rng_get_shape(R.GENERATORS[name], R.DTYPES[d]) for name, d in launches]
+    layout = layout_ceiling(torch, R, dev, out, shapes)
 
     extra = {} if args.no_extra else side_workloads(torch, R, dev, stream)
 
@@ -188,6 +190,8 @@ def main():
         "launch_shapes": tuned,
         "write_ceiling": ceil,
         "frac_of_write_ceiling": round(achieved / ceil["best_GB_s"], 4) if ceil else None,
+        "layout_write_ceiling": layout,
+        "frac_of_layout_ceiling": round(achieved / layout["GB_s"], 4),
         "per_kernel": {k: {kk: vv for kk, vv in v.items() if kk != "total_ms"} for k, v in per.items()},
         "side_workloads": extra,
         "served_latency_us": {k: {"p50": v["p50_us"], "p99": v["p99_us"]}
@@ -235,6 +239,26 @@ def write_ceiling(torch, dev):
     del buf
     torch.cuda.empty_cache()
     return res
+
+
+def layout_ceiling(torch, R, dev, out, shapes):
+    """Write rate of the generation kernel's own store schedule at the step's
+    size: rng_calibrate_store runs the same resident schedule, LDS transpose
+    and pipelined 16-byte stores with a counter in place of a generator (one
+    state word per stream, read and written back).  Best over the step's
+    launch shapes; algorithmic bytes as for a one-word generator."""
+    st = torch.zeros(S_BULK, dtype=torch.int32, device=dev)
+    nbytes = S_BULK * N_BULK * 4 + 2 * S_BULK * 4
+    best = None
+    for wg, un in sorted(set(shapes)):
+        ms = _time(torch, lambda: R.rng_calibrate_store(st, S_BULK, N_BULK, out, wg, un), 20, warm=3)
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        if best is None or gbs > best["GB_s"]:
+            best = {"GB_s": round(gbs, 1), "ms": round(ms, 4), "wg": wg, "unroll": un}
+    best["bytes"] = nbytes
+    best["kernel"] = "k_generate<counter> (store mode, rng_calibrate_store)"
+    del st
+    return best
 
 
 def _time(torch, fn, reps, warm=1):

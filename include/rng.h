@@ -129,6 +129,19 @@ int rng_autotune(int g, int t, uint64_t n_streams, uint64_t n, uint32_t *d_state
  * paper measured its achievable peaks the same way (Sec. V).  Synchronous. */
 int rng_calibrate_valu(int op, double *lane_ops_per_s, void *stream);
 
+/* Achievable write rate of the bulk store schedule (Sec. V measured its
+ * achievable bandwidth beside its kernels the same way): the generation
+ * kernel with its resident schedule, LDS transpose and pipelined 16-byte
+ * stores, run with a counter in place of a generator.  Sample k of stream s is
+ * d_state[s] + k + 1 (mod 2^32), written to d_out[s][k], and d_state[s]
+ * advances by n; every stream is one chunk.  d_state holds n_streams words,
+ * d_out n_streams x n words (16-byte aligned with n a multiple of 4 for the
+ * 128-bit stores), both owned by the caller; wg and unroll as for
+ * rng_generate_ex.  Asynchronous on stream.  RNG_EINVAL for a bad shape, NULL
+ * or misaligned pointers, RNG_ERANGE for sizes beyond 64-bit byte counts. */
+int rng_calibrate_store(uint32_t *d_state, uint64_t n_streams, uint64_t n, void *d_out, uint32_t wg,
+                        uint32_t unroll, void *stream);
+
 /* Advance every stream by k steps without producing output: sequence
  * splitting needs the i-th number without the intermediate ones (Sec.
  * II.A.4).  MWC: z <- a^k z mod (a*b - 1) with z = c*b + x; XorShift: the

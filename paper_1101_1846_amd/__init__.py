@@ -56,6 +56,7 @@ _SIGS = {
     "rng_generate_split": (_int, [_int, _vp, _u64, _u64, _int, _vp, _vp, _vp, _u64, _vp]),
     "rng_fused_pi": (_int, [_int, _vp, _u64, _u64, _vp, _vp]),
     "rng_calibrate_valu": (_int, [_int, ctypes.POINTER(ctypes.c_double), _vp]),
+    "rng_calibrate_store": (_int, [_vp, _u64, _u64, _vp, _u32, _u32, _vp]),
     "rng_xs256_placement": (_int, [_int, _vp, _u64, _u64, _int, _vp, _vp, _vp]),
     "rng_generate_fold": (_int, [_int, _vp, _u64, _u64, _int, _vp, _vp]),
     "rng_leapfrog_workspace_bytes": (_int, [_int, _u64, _pu64]),
@@ -267,6 +268,11 @@ def rng_calibrate_valu(op, stream=None):
     v = ctypes.c_double()
     _check(_lib.rng_calibrate_valu(op, ctypes.byref(v), _stream(stream)), "rng_calibrate_valu")
     return v.value
+
+
+def rng_calibrate_store(d_state, n_streams, n, d_out, wg, unroll, stream=None):
+    return _check(_lib.rng_calibrate_store(_ptr(d_state), n_streams, n, _ptr(d_out), wg, unroll, _stream(stream)),
+                  "rng_calibrate_store")
 
 
 def rng_batch_create(max_requests, max_samples):

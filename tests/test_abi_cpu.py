@@ -108,6 +108,17 @@ def test_fold_and_leapfrog_validation(rng):
         == rng.RNG_EINVAL  # workspace must be 256-byte aligned
 
 
+def test_calibrate_store_validation(rng):
+    L = rng.raw()
+    fake = 0x10000
+    assert L.rng_calibrate_store(fake, 64, 256, fake, 100, 4, None) == rng.RNG_EINVAL  # workgroup size
+    assert L.rng_calibrate_store(fake, 64, 256, fake, 256, 3, None) == rng.RNG_EINVAL  # unroll
+    assert L.rng_calibrate_store(None, 64, 256, fake, 256, 4, None) == rng.RNG_EINVAL
+    assert L.rng_calibrate_store(fake, 64, 256, fake + 2, 256, 4, None) == rng.RNG_EINVAL
+    assert L.rng_calibrate_store(None, 0, 256, None, 256, 4, None) == rng.RNG_OK
+    assert L.rng_calibrate_store(fake, 1 << 40, 1 << 40, fake, 256, 4, None) == rng.RNG_ERANGE
+
+
 def test_shape_roundtrip(rng):
     g, t = rng.RNG_XS32, rng.RNG_F32
     old = rng.rng_get_shape(g, t)
