@@ -197,6 +197,12 @@ def main():
         "served_latency_us": {k: {"p50": v["p50_us"], "p99": v["p99_us"]}
                               for k, v in extra.get("served", {}).items() if isinstance(v, dict)},
         "cpu_baseline": cpu,
+        "paper_reported": {
+            "hardware": "NVIDIA GTX280 (GT200), CUDA 2.3",
+            "GSamples_s_with_writeback": {"%s_%s" % (n, d): PAPER_WITH_WRITEBACK[n][i]
+                                          for n in PAPER_WITH_WRITEBACK for i, d in enumerate(("u32", "f32"))},
+            "note": "Tables II-III, about 4e7 numbers per call; context only (vs_baseline stays null)",
+        },
         "wall_s_timed": round(wall, 3),
     }
     print(json.dumps(line))
@@ -416,6 +422,9 @@ XS256_USEFUL_OPS = 18  # useful operations per XorShift number (11 XORs, 7 shift
 USEFUL_OPS = {"MWC32": 2, "MWC1616": 10, "XS32": 6, "XS256": 18, "KISS": 18}
 # The paper's GTX280 rates without write-back (integer, uniform), GSamples/s: context only.
 PAPER_NO_WRITEBACK = {"MWC1616": (37.5, 23.6), "XS256": (14.5, 12.9), "KISS": (19.1, 10.3)}
+# The paper's GTX280 rates with write-back (integer, uniform), GSamples/s, for the generators of the step
+# (Tables II and III; its XorShift with the state in registers): context only, other hardware and sizes.
+PAPER_WITH_WRITEBACK = {"XS256": (12.5, 11.5), "KISS": (9.2, 8.5)}
 
 
 def fold_workload(torch, R, dev):
