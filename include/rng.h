@@ -275,9 +275,10 @@ int rng_batch_launch(rng_batch_t *h, void *stream);
  * host time against 2.6 us per direct launch, so the direct launches give
  * the lower latency. */
 int rng_batch_set_graph(rng_batch_t *h, int use_graph);
-/* Persistent-kernel shape: wg lanes per workgroup (64..512), unroll
- * (samples per generation step) and chunk length C (a multiple of 64);
- * 0 keeps the current value.  chunk = RNG_BATCH_CHUNK_AUTO lets every plan
+/* Persistent-kernel shape: wg lanes per workgroup and unroll (samples per
+ * generation step), one of the built pairs: wg 64, 128, 256 or 512 with
+ * unroll 8, and unroll 1, 2, 4 or 16 with wg 256 (other pairs RNG_EINVAL);
+ * and chunk length C (a multiple of 64).  0 keeps the current value.  chunk = RNG_BATCH_CHUNK_AUTO lets every plan
  * choose C: the power of two in [64, 4096] that cuts the batch into about
  * 2^17 chunks (as many 64-chunk tiles as the device holds waves), so that
  * small batches still spread over the device; the workspace is sized for
