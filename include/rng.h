@@ -135,10 +135,11 @@ int rng_calibrate_valu(int op, double *lane_ops_per_s, void *stream);
  * stores, run with a counter in place of a generator.  Sample k of stream s is
  * d_state[s] + k + 1 (mod 2^32), written to d_out[s][k], and d_state[s]
  * advances by n; every stream is one chunk.  d_state holds n_streams words,
- * d_out n_streams x n words (16-byte aligned with n a multiple of 4 for the
- * 128-bit stores), both owned by the caller; wg and unroll as for
- * rng_generate_ex.  Asynchronous on stream.  RNG_EINVAL for a bad shape, NULL
- * or misaligned pointers, RNG_ERANGE for sizes beyond 64-bit byte counts. */
+ * d_out n_streams x n words, both 4-byte aligned and owned by the caller (a
+ * 16-byte aligned d_out with n a multiple of 4 takes the 128-bit stores); wg
+ * and unroll as for rng_generate_ex.  Asynchronous on stream.  RNG_EINVAL for
+ * a bad shape, NULL or misaligned pointers, RNG_ERANGE for sizes the ABI's
+ * size checks reject (as rng_generate). */
 int rng_calibrate_store(uint32_t *d_state, uint64_t n_streams, uint64_t n, void *d_out, uint32_t wg,
                         uint32_t unroll, void *stream);
 
