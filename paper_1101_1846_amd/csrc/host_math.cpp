@@ -218,6 +218,20 @@ static HostTables *build_tables()
     delete M;
     T->xs256_t4.resize((size_t)kPowBits * 8192);
     for (int b = 0; b < kPowBits; ++b) xs256_nibble_table(&T->xs256_pow[(size_t)b * 2048], &T->xs256_t4[(size_t)b * 8192]);
+    // One table per hexadecimal digit d != 0 at position j: a jump by k then
+    // takes one product per nonzero digit of k instead of one per set bit.
+    T->xs256_t4w.resize((size_t)16 * 15 * 8192);
+    auto *base = new Gf2Mat<8>, *P = new Gf2Mat<8>;
+    for (int j = 0; j < 16; ++j) {
+        std::memcpy(base->c, &T->xs256_pow[(size_t)(4 * j) * 2048], sizeof(base->c));
+        *P = *base;
+        for (int d = 1; d <= 15; ++d) {
+            if (d > 1) *P = (*P) * (*base);
+            xs256_nibble_table(&P->c[0][0], &T->xs256_t4w[((size_t)j * 15 + (d - 1)) * 8192]);
+        }
+    }
+    delete base;
+    delete P;
     return T;
 }
 

@@ -49,6 +49,7 @@ struct HostTables {
     uint32_t mwc16_pow_fold[kMwc16Count][kPowBits];  // a_i^(2^b) * 2^48 mod m_i
     std::vector<uint32_t> xs256_pow;           // [64][256][8]: M^(2^b)
     std::vector<uint32_t> xs256_t4;            // [64][64][2][16][4]: 4-bit lookup tables of M^(2^b)
+    std::vector<uint32_t> xs256_t4w;           // [16][15][8192]: 4-bit lookup tables of M^(d 16^j), d = 1..15
 };
 
 // 4-bit lookup table of a 256x256 GF(2) matrix given by its 256 columns of 8

@@ -67,7 +67,8 @@ int device_tables(DevTables *out)
         const size_t o_m16 = o_x32 + n_x32, n_m16 = sizeof(H.mwc16_pow_fold);
         const size_t o_x256 = (o_m16 + n_m16 + 255) & ~(size_t)255;
         const size_t n_x256 = H.xs256_t4.size() * sizeof(uint32_t);
-        const size_t total = o_x256 + n_x256;
+        const size_t o_x256w = o_x256 + n_x256, n_x256w = H.xs256_t4w.size() * sizeof(uint32_t);
+        const size_t total = o_x256w + n_x256w;
         std::string host(total, '\0');
         std::memcpy(&host[o_t392], H.t392, n_t392);
         std::memcpy(&host[o_m32], H.mwc32_pow_fold, n_m32);
@@ -75,6 +76,7 @@ int device_tables(DevTables *out)
         std::memcpy(&host[o_x32], H.xs32_pow, n_x32);
         std::memcpy(&host[o_m16], H.mwc16_pow_fold, n_m16);
         std::memcpy(&host[o_x256], H.xs256_t4.data(), n_x256);
+        std::memcpy(&host[o_x256w], H.xs256_t4w.data(), n_x256w);
         void *blob = nullptr;
         if ((e = hipMalloc(&blob, total)) != hipSuccess) return hip_fail(e, "hipMalloc(tables)");
         if ((e = hipMemcpy(blob, host.data(), total, hipMemcpyHostToDevice)) != hipSuccess) {
@@ -88,6 +90,7 @@ int device_tables(DevTables *out)
         d.tab.xs32_pow = (const uint32_t *)(b + o_x32);
         d.tab.mwc16_pow = (const uint32_t *)(b + o_m16);
         d.tab.xs256_t4 = (const uint4 *)(b + o_x256);
+        d.tab.xs256_t4w = (const uint4 *)(b + o_x256w);
         d.tab.mwc32_a = H.mwc32_a;
         d.tab.mwc32_m = H.mwc32_m;
         d.blob = blob;

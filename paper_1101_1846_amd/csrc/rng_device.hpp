@@ -22,6 +22,7 @@ struct DevTables {
     const uint32_t *xs32_pow;      // [64][32] columns of M^(2^b)
     const uint32_t *mwc16_pow;     // [392][64] a_i^(2^b) * 2^48 mod m_i
     const uint4 *xs256_t4;         // [64][64][2][16] 4-bit lookup tables of M^(2^b)
+    const uint4 *xs256_t4w;        // [16][15][64][2][16] 4-bit lookup tables of M^(d 16^j), d = 1..15
     uint32_t mwc32_a;              // 65274
     uint64_t mwc32_m;              // a * 2^32 - 1
 };
@@ -185,10 +186,14 @@ struct GenXS256 : rng_inline::XS256 {
     {
         load(st, S, s);
     }
+    // M^k v as one product per nonzero hexadecimal digit d_j of k, by the
+    // table of M^(d_j 16^j) (the powers commute, so the order is free).
     __device__ void jump(uint64_t k, const DevTables &tab)
     {
-        for (int b = 0; b < 64 && (k >> b); ++b)
-            if ((k >> b) & 1) gf2_apply256_t4(tab.xs256_t4 + (size_t)b * 2048, v);
+        for (int j = 0; j < 16 && (k >> (4 * j)); ++j) {
+            const uint32_t d = (uint32_t)(k >> (4 * j)) & 15u;
+            if (d) gf2_apply256_t4(tab.xs256_t4w + ((size_t)j * 15 + (d - 1)) * 2048, v);
+        }
     }
     // One jump by the power of two whose lookup table T holds (staged in LDS).
     __device__ __forceinline__ void jump_table(const uint4 *T) { gf2_apply256_t4(T, v); }

@@ -10,11 +10,12 @@
 //   XS256    M^k v by 64 nibble lookups                     (LDS table of M^k)
 //   LCG      X <- A_k X + C_k                               (host constants)
 // The XS256 table is built per workgroup: thread c carries column c of the
-// identity through the staged table of M^(2^b) for every set bit b of k, and
-// the 256 columns then give the nibble table of M^k.  That costs about 5 us
-// per set bit of k whatever the number of states, so below kXs256TableMin
-// states every state jumps on its own (one product per set bit, from the
-// global power tables), which is as fast there and has a lower latency floor.
+// identity through the staged table of M^(d 16^j) for every nonzero
+// hexadecimal digit d at position j of k, and the 256 columns then give the
+// nibble table of M^k.  That costs a few us per nonzero digit of k whatever
+// the number of states, so below kXs256TableMin states every state jumps on
+// its own (one product per nonzero digit, from the global tables), which is
+// as fast there and has a lower latency floor.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -91,17 +92,22 @@ __global__ __launch_bounds__(kSkipWG) void k_skip_by(SkipArgs a)
         uint32_t col[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) col[i] = (uint32_t)(tid / 32 == (uint32_t)i) << (tid % 32);
-        // Set bits of k in increasing order (uniform: k is the same for every
-        // thread).  The table of the next one is loaded into registers while
-        // the current one is applied; buffer b & 1 is rewritten only after the
-        // barrier that follows the previous write, which every thread reaches
-        // after applying what that buffer held before.
+        // Nonzero hexadecimal digits of k in increasing position (uniform: k
+        // is the same for every thread).  The table of the next one is loaded
+        // into registers while the current one is applied; buffer b & 1 is
+        // rewritten only after the barrier that follows the previous write,
+        // which every thread reaches after applying what that buffer held.
         constexpr int Q = 2048 / kSkipWG;
+        uint32_t rest = 0;  // non-zero: the host returns before launching for k = 0
+        for (int j = 0; j < 16; ++j)
+            if ((a.k >> (4 * j)) & 15) rest |= 1u << j;
+        auto table = [&](int j) {
+            return a.tab.xs256_t4w + ((size_t)j * 15 + (((a.k >> (4 * j)) & 15) - 1)) * 2048;
+        };
         uint4 pre[Q];
-        uint64_t rest = a.k;  // non-zero: the host returns before launching for k = 0
-        int b = __builtin_ctzll(rest);
+        const uint4 *src = table(__builtin_ctz(rest));
 #pragma unroll
-        for (int i = 0; i < Q; ++i) pre[i] = a.tab.xs256_t4[(size_t)b * 2048 + tid + i * kSkipWG];
+        for (int i = 0; i < Q; ++i) pre[i] = src[tid + i * kSkipWG];
         for (uint32_t buf = 0;; buf ^= 1) {
             uint4 *t = s_t4 + buf * 2048;
 #pragma unroll
@@ -109,9 +115,9 @@ __global__ __launch_bounds__(kSkipWG) void k_skip_by(SkipArgs a)
             __syncthreads();
             rest &= rest - 1;
             if (rest) {
-                b = __builtin_ctzll(rest);
+                src = table(__builtin_ctz(rest));
 #pragma unroll
-                for (int i = 0; i < Q; ++i) pre[i] = a.tab.xs256_t4[(size_t)b * 2048 + tid + i * kSkipWG];
+                for (int i = 0; i < Q; ++i) pre[i] = src[tid + i * kSkipWG];
             }
             gf2_apply256_t4(t, col);
             if (!rest) break;
@@ -175,7 +181,8 @@ int launch_skip_by(const SkipArgs &a, hipStream_t stream)
         return hipGetLastError() == hipSuccess ? 0 : -1;
     }
     // workgroups that build LDS tables stride over the states: one per CU
-    // for XS256 (one staged table per set bit of k), two for MWC16
+    // for XS256 (one staged table per nonzero hexadecimal digit of k), two
+    // for MWC16
     const uint64_t cap = G::kId == G_XS256 ? 256 : (G::kId == G_MWC1616 || G::kId == G_KISS) ? 512 : 4096;
     const uint64_t need = (a.S + kSkipWG - 1) / kSkipWG;
     const unsigned blocks = (unsigned)(need < cap ? need : cap);
