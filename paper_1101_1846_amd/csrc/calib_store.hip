@@ -18,11 +18,10 @@ namespace rngx {
 namespace {
 
 // Sample k of a stream whose state word is y is y + k + 1 (mod 2^32), and the
-// state advances by the number of samples.  kId takes xorshift32's value
-// only because the rotated-order code dispatches on it for one-word states;
-// the calibration never takes that order (its launches leave rot at 0).
+// state advances by the number of samples.  Its id is no generator's, so the
+// kernel takes none of the generator-specific paths (the rotated row order).
 struct GenCount {
-    static constexpr int kId = G_XS32, W = 1, D = 1;
+    static constexpr int kId = 0, W = 1, D = 1;
     uint32_t y;
     __device__ __forceinline__ void load(const uint32_t *st, uint64_t, uint64_t s, const DevTables &) { y = st[s]; }
     __device__ __forceinline__ void store(uint32_t *st, uint64_t, uint64_t s) const { st[s] = y; }

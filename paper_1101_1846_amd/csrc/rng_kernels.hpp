@@ -573,7 +573,8 @@ int launch_generate_shape(const GenArgs &a, hipStream_t stream)
         }
     }
     bool launched = false;
-    if constexpr (kMode == 2 && K == 128 && G::kId != G_XS256) {
+    if constexpr (kMode == 2 && K == 128 &&
+                  (G::kId == G_MWC32 || G::kId == G_XS32 || G::kId == G_KISS || G::kId == G_MWC1616)) {
         if (b.resident && a.rot) {
             hipLaunchKernelGGL((k_generate_rot<G, DT, WG, U>), dim3((unsigned)blocks), dim3(WG), 0, stream, b);
             launched = true;
