@@ -166,7 +166,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32",
+        "dtype": "u32+f32",
         "data": "synthetic: per-stream states from SplitMix64(seed=1), no dataset",
         "config": {
             "workload": "bulk store mode: XS256 (eq. 5), XS32 (eq. 6), KISS; 2^20 streams x 256 samples; "
@@ -625,37 +625,102 @@ def served_workload(R, single_rate):
     return out
 
 
+def host_cpu():
+    """CPU model, logical CPUs, and the CPUs this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = os.cpu_count() or 1
+    return {"model": model, "nproc": os.cpu_count(), "affinity": allowed}
+
+
+# A one-GPU job may use this many host cores (the host's share per GPU), whatever
+# the machine reports: the all-cores legs use min(affinity, this).
+HOST_CORES_PER_GPU = 16
+
+
 def cpu_baseline(seconds):
-    """The serial oracle on the host's cores over a bounded sample of the step's
-    workload: whole streams of 256 samples for every generator and dtype of the
-    step, streams split over host threads, repeated until about `seconds` of
-    wall time, scaled to GSamples/s."""
+    """The serial oracle on the host over a bounded sample of the step's
+    workload: whole streams of 256 samples for every generator and dtype of
+    the step, streams split over host threads.  Four legs, each repeated
+    until about seconds / 4 of wall time: the oracle as built for the tests
+    (gcc -O2, the paper's CPU optimisation level) and the same source at
+    -O3 -march=native (built here, for this CPU), each on one thread (the
+    paper's single-thread CPU rows) and on all the cores the job may use.
+    ``value`` is the -O2 all-cores leg: the oracle as it stands."""
+    import tempfile
+
     import oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
-    gens = [(oracle.GENERATORS[n], d) for n in STEP_GENS for d in (oracle.U32, oracle.F32)]
+    cpu = host_cpu()
+    cores = max(1, min(cpu["affinity"], HOST_CORES_PER_GPU))
     oracle.mwc16_table()  # one-time table search, not part of the rate
+    variants = {"gcc -O2": oracle.lib()}
+    tmpdir = tempfile.mkdtemp(prefix="oracle_o3_")
+    try:
+        path = oracle.build_variant(os.path.join(tmpdir, "liboracle_o3native.so"), ["-O3", "-march=native"])
+        variants["gcc -O3 -march=native"] = oracle.lib(path)
+    except Exception as e:  # noqa: BLE001 - the leg is reported as missing
+        variants["gcc -O3 -march=native"] = "build failed: %s" % e
+    gens = [(n, d) for n in STEP_GENS for d in ("u32", "f32")]
+    budget = seconds / 4.0
 
-    def run(S):
-        t = time.perf_counter()
-        for g, d in gens:
+    def run(L, S, threads):
+        per = {}
+        for n, d in gens:
+            g = oracle.GENERATORS[n]
             st = oracle.seed(g, 1, S)
-            oracle.generate(g, st, N_BULK, d, threads=threads)
-        return time.perf_counter() - t
+            t = time.perf_counter()
+            oracle.generate(g, st, N_BULK, oracle.F32 if d == "f32" else oracle.U32, threads=threads, library=L)
+            per["%s_%s" % (n, d)] = time.perf_counter() - t
+        return per
 
-    S = 1 << 14
-    run(S)  # warm-up: thread start, page faults
-    dt = run(S)
-    # one pass of about a tenth of the budget, repeated until the budget is spent
-    S = int(min(S_BULK, max(S, S * 0.1 * seconds / max(dt, 1e-3))))
-    S = max(threads, S // threads * threads)
-    reps, total_t, samples = 0, 0.0, 0
-    while total_t < seconds and reps < 1000:
-        total_t += run(S)
-        samples += len(gens) * S * N_BULK
-        reps += 1
-    return {"value": round(samples / total_t / 1e9, 4), "unit": "GSamples/s", "cores": threads, "kind": "oracle",
-            "sample": "%d pass(es) over %d streams x %d samples for each of %d (generator, dtype) pairs of the "
-                      "step, %.1f s of wall time" % (reps, S, N_BULK, len(gens), total_t)}
+    legs = []
+    for flags, L in variants.items():
+        for threads in (1, cores):
+            if isinstance(L, str):
+                legs.append({"flags": flags, "threads": threads, "error": L})
+                continue
+            S = 1 << 12
+            run(L, S, threads)  # warm-up: thread start, page faults
+            dt = sum(run(L, S, threads).values())
+            # one pass of about a fifth of the leg's budget, repeated until it is spent
+            S = int(min(S_BULK, max(S, S * 0.2 * budget / max(dt, 1e-3))))
+            S = max(threads, S // threads * threads)
+            reps, tot = 0, {}
+            while sum(tot.values()) < budget and reps < 1000:
+                for k, v in run(L, S, threads).items():
+                    tot[k] = tot.get(k, 0.0) + v
+                reps += 1
+            t_all = sum(tot.values())
+            legs.append({"flags": flags, "threads": threads,
+                         "GSamples_s": round(reps * len(gens) * S * N_BULK / t_all / 1e9, 4),
+                         "per_generator_GSamples_s": {k: round(reps * S * N_BULK / v / 1e9, 4) for k, v in tot.items()},
+                         "sample": "%d pass(es) over %d streams x %d samples per (generator, dtype), %.1f s"
+                                   % (reps, S, N_BULK, t_all)})
+    try:
+        for f in os.listdir(tmpdir):
+            os.remove(os.path.join(tmpdir, f))
+        os.rmdir(tmpdir)
+    except OSError:
+        pass
+    head = next(l for l in legs if l["flags"] == "gcc -O2" and l["threads"] == cores)
+    return {"value": head["GSamples_s"], "unit": "GSamples/s", "cores": cores, "kind": "oracle",
+            "sample": "%s; the step's 6 (generator, dtype) pairs, gcc -O2, %d threads" % (head["sample"], cores),
+            "cpu_model": cpu["model"], "nproc": cpu["nproc"], "affinity_cpus": cpu["affinity"],
+            "cores_note": "all-cores legs use min(affinity, %d): the host cores one GPU's job may use"
+                          % HOST_CORES_PER_GPU,
+            "legs": legs,
+            "paper_single_thread_cpu_GSamples_s": {"hardware": "Xeon Q6600, MSVC 2005 -O2",
+                                                   "MWC": 0.3, "XorShift": 0.1, "KISS": 0.2}}
 
 
 KERNEL_SOURCES = ["paper_1101_1846_amd/csrc/rng_device.hpp", "paper_1101_1846_amd/csrc/rng_kernels.hpp",

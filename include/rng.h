@@ -126,7 +126,8 @@ int rng_autotune(int g, int t, uint64_t n_streams, uint64_t n, uint32_t *d_state
 /* Measured 32-bit integer VALU rate of the current device in lane-operations
  * per second, for op 0 (add + xor), 1 (24-bit multiply-add), 2 (32-bit
  * multiply low): eight independent chains per lane on every SIMD.  The
- * paper measured its achievable peaks the same way (Sec. V).  Synchronous. */
+ * paper derived its integer peak as a third of the FP rate (Sec. V) and
+ * measured only bandwidth; this measures the integer rate.  Synchronous. */
 int rng_calibrate_valu(int op, double *lane_ops_per_s, void *stream);
 
 /* Achievable write rate of the bulk store schedule (Sec. V measured its

@@ -39,44 +39,60 @@ def build(force=False):
     return _LIB
 
 
-def lib():
+def build_variant(path, flags):
+    """Compile the same source with other optimisation flags into ``path``
+    (for timing only: e.g. -O3 -march=native, built on the machine that runs
+    it, since -march=native code may not run on another CPU)."""
+    tmp = path + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc"] + list(flags) + ["-std=c11", "-shared", "-fPIC", "-o", tmp, _SRC])
+    os.replace(tmp, path)
+    return path
+
+
+def _bind(L):
+    sig = {
+        "orc_mwc16_table": (ctypes.c_int, [u16p, ctypes.c_int]),
+        "orc_mwc32_multiplier": (ctypes.c_uint32, []),
+        "orc_is_prime": (ctypes.c_int, [c_u64]),
+        "orc_sm64_next": (c_u64, [u64p]),
+        "orc_step_mwc32": (ctypes.c_uint32, [ctypes.c_uint32, u32p, u32p]),
+        "orc_step_mwc16": (ctypes.c_uint32, [ctypes.c_uint32, u32p]),
+        "orc_step_mwc1616": (ctypes.c_uint32, [ctypes.c_uint32, ctypes.c_uint32, u32p, u32p]),
+        "orc_step_xs32": (ctypes.c_uint32, [u32p]),
+        "orc_step_lcg": (ctypes.c_uint32, [u32p]),
+        "orc_step_xs256": (ctypes.c_uint32, [u32p]),
+        "orc_step_kiss": (ctypes.c_uint32, [ctypes.c_uint32, ctypes.c_uint32, u32p, u32p, u32p, u32p]),
+        "orc_to_f32": (ctypes.c_float, [ctypes.c_uint32]),
+        "orc_state_words": (ctypes.c_int, [ctypes.c_int]),
+        "orc_seed": (None, [ctypes.c_int, c_u64, c_u64, c_u64, u32p]),
+        "orc_generate_range": (None, [ctypes.c_int, u32p, c_u64, c_u64, c_u64, c_u64, ctypes.c_int, ctypes.c_void_p]),
+        "orc_generate": (None, [ctypes.c_int, u32p, c_u64, c_u64, ctypes.c_int, ctypes.c_void_p]),
+        "orc_serial_sample": (None, [ctypes.c_int, u32p, c_u64, u64p, c_u64, u32p, c_u64, u32p, c_u64, u32p]),
+        "orc_fused_pi_range": (c_u64, [ctypes.c_int, u32p, c_u64, c_u64, c_u64, c_u64]),
+        "orc_skip_big": (None, [ctypes.c_int, u32p, c_u64, u32p, ctypes.c_int]),
+        "orc_skip": (None, [ctypes.c_int, u32p, c_u64, c_u64]),
+        "orc_period_xs32": (c_u64, [ctypes.c_uint32]),
+        "orc_period_lcg": (c_u64, [ctypes.c_uint32]),
+        "orc_period_mwc16": (c_u64, [ctypes.c_uint32, ctypes.c_uint32]),
+        "orc_period_mwc_small": (c_u64, [ctypes.c_uint32, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+def lib(path=None):
+    """The oracle library; ``path`` loads a variant built by build_variant()."""
     global _lib
+    if path is not None:
+        return _bind(ctypes.CDLL(path))
     with _lock:
         if _lib is None:
             if not os.path.exists(_LIB):
                 build()
-            L = ctypes.CDLL(_LIB)
-            sig = {
-                "orc_mwc16_table": (ctypes.c_int, [u16p, ctypes.c_int]),
-                "orc_mwc32_multiplier": (ctypes.c_uint32, []),
-                "orc_is_prime": (ctypes.c_int, [c_u64]),
-                "orc_sm64_next": (c_u64, [u64p]),
-                "orc_step_mwc32": (ctypes.c_uint32, [ctypes.c_uint32, u32p, u32p]),
-                "orc_step_mwc16": (ctypes.c_uint32, [ctypes.c_uint32, u32p]),
-                "orc_step_mwc1616": (ctypes.c_uint32, [ctypes.c_uint32, ctypes.c_uint32, u32p, u32p]),
-                "orc_step_xs32": (ctypes.c_uint32, [u32p]),
-                "orc_step_lcg": (ctypes.c_uint32, [u32p]),
-                "orc_step_xs256": (ctypes.c_uint32, [u32p]),
-                "orc_step_kiss": (ctypes.c_uint32, [ctypes.c_uint32, ctypes.c_uint32, u32p, u32p, u32p, u32p]),
-                "orc_to_f32": (ctypes.c_float, [ctypes.c_uint32]),
-                "orc_state_words": (ctypes.c_int, [ctypes.c_int]),
-                "orc_seed": (None, [ctypes.c_int, c_u64, c_u64, c_u64, u32p]),
-                "orc_generate_range": (None, [ctypes.c_int, u32p, c_u64, c_u64, c_u64, c_u64, ctypes.c_int, ctypes.c_void_p]),
-                "orc_generate": (None, [ctypes.c_int, u32p, c_u64, c_u64, ctypes.c_int, ctypes.c_void_p]),
-                "orc_serial_sample": (None, [ctypes.c_int, u32p, c_u64, u64p, c_u64, u32p, c_u64, u32p, c_u64, u32p]),
-                "orc_fused_pi_range": (c_u64, [ctypes.c_int, u32p, c_u64, c_u64, c_u64, c_u64]),
-                "orc_skip_big": (None, [ctypes.c_int, u32p, c_u64, u32p, ctypes.c_int]),
-                "orc_skip": (None, [ctypes.c_int, u32p, c_u64, c_u64]),
-                "orc_period_xs32": (c_u64, [ctypes.c_uint32]),
-                "orc_period_lcg": (c_u64, [ctypes.c_uint32]),
-                "orc_period_mwc16": (c_u64, [ctypes.c_uint32, ctypes.c_uint32]),
-                "orc_period_mwc_small": (c_u64, [ctypes.c_uint32, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32]),
-            }
-            for name, (res, args) in sig.items():
-                f = getattr(L, name)
-                f.restype = res
-                f.argtypes = args
-            _lib = L
+            _lib = _bind(ctypes.CDLL(_LIB))
     return _lib
 
 
@@ -105,14 +121,15 @@ def seed(gen, seed_value, n_streams, first_stream=0):
     return st
 
 
-def generate(gen, state, n, dtype=U32, threads=1):
+def generate(gen, state, n, dtype=U32, threads=1, library=None):
     """Serial per stream; ``threads`` > 1 splits whole streams over host threads
-    (ctypes releases the GIL).  ``state`` is advanced in place."""
+    (ctypes releases the GIL).  ``state`` is advanced in place.  ``library``:
+    a variant from lib(path) (same source, other compiler flags)."""
     S = state.shape[1]
     out = np.empty((S, n), dtype=np.float32 if dtype == F32 else np.uint32)
     if S == 0 or n == 0:
         return out
-    L = lib()
+    L = library or lib()
     if threads <= 1 or S < threads:
         L.orc_generate_range(gen, _p32(state), S, 0, S, n, dtype, out.ctypes.data)
         return out

@@ -4,7 +4,7 @@
 // Each thread starts at state_j (a radix-16 tree of jumps, as for sequence
 // splitting), steps once, and then leaps T steps per number with the
 // generator's T-step map:
-//   MWC32    z <- (a^T mod m) z mod m         one fold-domain multiply (eq. (4))
+//   MWC32    z <- (a^T mod m) z mod m         one fold-domain multiply (eqs. (2)-(3))
 //   MWC1616  z, w <- a_i^T z mod m_i           two; constants from the state's multipliers
 //   XS32     y <- M^T y                        32x32 GF(2) product, byte tables in LDS
 //   XS256    v <- M^T v                        256x256 GF(2) product, 4-bit table in LDS

@@ -1,6 +1,8 @@
-// rng_calib.hip -- device calibration of the integer VALU rate, the analogue
-// of the paper's measured "achievable" peaks (Sec. V): eight independent
-// accumulator chains per lane keep every SIMD busy with one opcode class.
+// rng_calib.hip -- device calibration of the integer VALU rate.  The paper
+// derived its integer-operation peak from the FP rate (one third of the
+// FLOP figure, Sec. V) and measured only its memory bandwidth; here the
+// integer rate is measured: independent accumulator chains per lane keep
+// every SIMD busy with one opcode class.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 

@@ -1,5 +1,5 @@
 // skip.hip -- jump-ahead of many states by one distance k (Sec. II.A.4: the
-// MWC congruence z <- a^k z mod m of eq. (4), the k-th power of the GF(2)
+// MWC congruence z <- a^k z mod m that follows from eqs. (2)-(3), the k-th power of the GF(2)
 // step matrix of eqs. (5) and (6), and the affine LCG map).  Every state moves
 // by the same k, so the k-step map is built once -- on the host for the
 // constants that do not depend on the state, once per workgroup in LDS for

@@ -75,7 +75,9 @@ def test_placement_bench_size(rng, torch, oracle):
         outs.append(out.view(N, S))
     assert torch.equal(outs[0], outs[2]) and torch.equal(outs[1], outs[2])
     pick = np.sort(np.random.default_rng(5).choice(S, 2000, replace=False))
-    for s in pick[:2000:100]:
-        one = oracle.seed(oracle.XS256, 33, 1, first_stream=int(s))
-        ref = oracle.generate(oracle.XS256, one, N)[0]
-        assert np.array_equal(_u32(outs[2][:, int(s)].contiguous()), ref), s
+    start = np.concatenate([oracle.seed(oracle.XS256, 33, 1, first_stream=int(s)) for s in pick], axis=1)
+    ref = oracle.generate(oracle.XS256, np.ascontiguousarray(start), N, threads=4)  # [2000][N]
+    got = _u32(outs[2][:, torch.from_numpy(pick).to(outs[2].device)].t().contiguous())
+    assert got.shape == ref.shape
+    bad = np.argwhere(got != ref)
+    assert bad.size == 0, "stream %d sample %d" % (pick[bad[0][0]], bad[0][1])

@@ -239,8 +239,62 @@ def test_xs256_matches_eq5_matrix_form(oracle):
         assert np.array_equal(w[:7], v[1:]) and w[7] == expect
 
 
+def test_xs32_matches_eq6_matrix_form(oracle):
+    """Eq. (6) read as matrices: A_1 = (I+L^13)(I+R^17)(I+L^5) in Marsaglia's
+    row-vector convention (the generator the paper takes from him, Sec.
+    II.A.3), so a state y advances as y <- y A_1, the left factor acting first.
+    L and R are built as 32x32 bit matrices with y L = y << 1 and y R = y >> 1,
+    and y A_1 is compared with the oracle's step on random and edge words.
+    The comparison tells the readings apart: the column-vector order (y <- A_1
+    y, <<5 first), L and R exchanged, and every triple with one shift changed
+    by one all differ from the oracle on these words, so a transposed order or
+    a wrong constant in the oracle cannot pass it."""
+    def shift_row(k, left):
+        # row-vector convention: (y M)_j = sum_i y_i M[i, j]; bit i moves to i +- k
+        M = np.zeros((32, 32), dtype=np.uint8)
+        for i in range(32):
+            j = i + k if left else i - k
+            if 0 <= j < 32:
+                M[i, j] = 1
+        return M
+    I = np.eye(32, dtype=np.uint8)
+    mm = lambda A, B: (A.astype(np.int64) @ B.astype(np.int64) % 2).astype(np.uint8)
+
+    def a1(a, b, c):
+        return mm(mm(I ^ shift_row(a, True), I ^ shift_row(b, False)), I ^ shift_row(c, True))
+
+    def bits(v):
+        return np.array([(v >> i) & 1 for i in range(32)], dtype=np.uint8)
+
+    def word(bv):
+        return int(sum(int(b) << i for i, b in enumerate(bv)))
+
+    A = a1(13, 17, 5)
+    rng = np.random.default_rng(6)
+    words = [1, 2, 0x80000000, 0xFFFFFFFF, 0x12345678] + [int(x) for x in rng.integers(1, 1 << 32, 60)]
+    L = oracle.lib()
+    for y0 in words:
+        y = ctypes.c_uint32(y0)
+        got = L.orc_step_xs32(ctypes.byref(y))
+        expect = word(mm(bits(y0).reshape(1, 32), A).ravel())
+        assert got == expect and y.value == expect, hex(y0)
+    # the pin discriminates: other orders and neighbouring triples differ
+    # from the oracle on these words
+    stepped = []
+    for y0 in words:
+        y = ctypes.c_uint32(y0)
+        stepped.append(L.orc_step_xs32(ctypes.byref(y)))
+    wrong = [A.T.copy()]  # L and R exchanged (the bit-reversed reading of L)
+    for d in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+        wrong.append(a1(13 + d[0], 17 + d[1], 5 + d[2]))
+    wrong.append(a1(5, 17, 13))  # column vectors, y <- A_1 y: <<5 first
+    for W in wrong:
+        alt = [word(mm(bits(y0).reshape(1, 32), W).ravel()) for y0 in words]
+        assert alt != stepped
+
+
 # ---------------------------------------------------------------- jump-ahead
-ALL_GENS = ["MWC32", "XS256", "XS32", "KISS", "MWC1616"]
+ALL_GENS =["MWC32", "XS256", "XS32", "KISS", "MWC1616"]
 
 
 @pytest.mark.parametrize("name", ALL_GENS)
