@@ -152,11 +152,37 @@ def test_autotune_keeps_values(rng, torch, oracle):
     rng.rng_set_shape(g, rng.RNG_U32, *old)
 
 
+def _check_requests(oracle, tab, names, where, offs, idx, host_out, base_word, host_pools, seed):
+    """Every sample and the final state of requests idx against the oracle:
+    the output from one serial pass from the stream's seeded state, the final
+    state from the oracle's jump-ahead by the request's length."""
+    bad = []
+    for i in idx:
+        g = names[tab["gen"][i]]
+        o = oracle.GENERATORS[g]
+        n = int(tab["length"][i])
+        st0 = oracle.seed(o, seed, 1, first_stream=where[i][2])
+        st = st0.copy()
+        ref = oracle.generate(o, st, n, int(tab["dtype"][i]))[0].view(np.uint32)
+        a = int(offs[i]) - base_word
+        if not np.array_equal(host_out[a:a + n], ref):
+            k = int(np.argmax(host_out[a:a + n] != ref))
+            bad.append("request %d (%s, length %d): sample %d differs" % (i, g, n, k))
+            continue
+        fin = oracle.skip(o, st0, n)
+        if not (np.array_equal(fin, st) and np.array_equal(host_pools[g][:, where[i][2]], fin[:, 0])):
+            bad.append("request %d (%s): final state differs" % (i, g))
+    return bad
+
+
 def test_batched_10k_requests(rng, torch, oracle):
     """The batched workload (10^4 requests, MWC32/XS256/KISS, u32/f32 50/50,
-    length log-uniform in [2^8, 2^22]) after autotuning the shape as bench.py
-    does: 200 sampled requests plus the 5 longest and 5 shortest, every sample
-    and final state."""
+    length log-uniform in [2^8, 2^22], 4.3e9 samples) after autotuning the
+    shape as bench.py does: every sample of every request, streamed to the host
+    in slices of about 2^28 samples, and every request's final state."""
+    import concurrent.futures
+    import sys
+
     import bench
     from paper_1101_1846_amd import workloads as W
     tab = W.batch_table(10000, seed=4)
@@ -177,17 +203,26 @@ def test_batched_10k_requests(rng, torch, oracle):
         rng.rng_batch_set(h, reqs)
         rng.rng_batch_launch(h)
         torch.cuda.synchronize()
-        order = np.argsort(tab["length"])
-        pick = set(np.random.default_rng(1).choice(len(reqs), 200, replace=False).tolist())
-        pick |= set(order[:5].tolist()) | set(order[-5:].tolist())
-        host_pools = {g: _u32(p) for g, p in pools.items()}
-        for i in sorted(pick):
-            g = names[tab["gen"][i]]
-            o = oracle.GENERATORS[g]
-            st = oracle.seed(o, 5, 1, first_stream=where[i][2])
-            ref = oracle.generate(o, st, int(tab["length"][i]), int(tab["dtype"][i]))[0].view(np.uint32)
-            got = _u32(out[int(offs[i]):int(offs[i]) + int(tab["length"][i])])
-            assert np.array_equal(got, ref), (i, g)
-            assert np.array_equal(host_pools[g][:, where[i][2]], st[:, 0]), (i, "state")
     finally:
         rng.rng_batch_destroy(h)
+    host_pools = {g: _u32(p) for g, p in pools.items()}
+    for g in names:  # the oracle's lazy tables are built before the threads start
+        oracle.seed(oracle.GENERATORS[g], 5, 1)
+    bad, i0, n_req = [], 0, len(reqs)
+    with concurrent.futures.ThreadPoolExecutor(THREADS) as ex:
+        while i0 < n_req:
+            i1, acc = i0, 0
+            while i1 < n_req and (acc < (1 << 28) or i1 == i0):
+                acc += int(tab["length"][i1])
+                i1 += 1
+            w0 = int(offs[i0])
+            w1 = int(offs[i1 - 1]) + int(tab["length"][i1 - 1])
+            host = _u32(out[w0:w1])
+            parts = np.array_split(np.arange(i0, i1), THREADS)
+            for r in ex.map(lambda idx: _check_requests(oracle, tab, names, where, offs, idx, host, w0,
+                                                        host_pools, 5), parts):
+                bad.extend(r)
+            print("batched parity: requests %d..%d checked" % (i0, i1 - 1), file=sys.stderr, flush=True)
+            assert not bad, bad[:5]
+            i0 = i1
+    assert i0 == 10000

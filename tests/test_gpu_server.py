@@ -129,3 +129,78 @@ def test_server_argument_errors(rng):
         assert rng.rng_server_poll(h, tk)[0]
     finally:
         rng.rng_server_destroy(h)
+
+
+def test_server_at_bench_scale(rng, hip, oracle):
+    """The served workload at the size bench.py runs it: 10^6 resident states
+    (generator = stream id mod 3 over MWC32/XS256/KISS), a 16 GiB output pool,
+    sizes log-uniform in [2^10, 2^24], dtype 50/50, Poisson arrivals at
+    20,000 requests/s, three batches in flight.  1200 requests (about 2e9
+    samples): every sample of every request against the oracle (requests on
+    one stream as consecutive slices in arrival order), the final state of
+    every touched stream, and untouched streams unchanged."""
+    import concurrent.futures
+    import os
+    import sys
+
+    from paper_1101_1846_amd import workloads as W
+    threads = max(1, min(16, os.cpu_count() or 1))
+    n_streams, seed, n = 10 ** 6, 8, 1200
+    gens = [rng.GENERATORS[k] for k in KINDS]
+    tab = W.served_table(n, seed=7)
+    t = W.poisson_arrivals(20000, n, seed=7)
+    assert int(tab["length"].sum()) * 4 < (16 << 30)  # every output fits the pool: no release needed
+    h = rng.rng_server_create(n_streams, gens, seed, 16 << 30, 4096, 1 << 31, inflight=3, auto_release=False,
+                              idle_spin_us=2000)
+    try:
+        tickets = rng.rng_server_replay(h, t, tab["stream"], tab["length"], tab["dtype"])
+        st = rng.rng_server_stats(h)
+        assert st["completed"] == n
+        print("served at scale: %d requests in %d batches, p50 %.0f us, p99 %.0f us"
+              % (n, st["batches"], st["p50_us"], st["p99_us"]), file=sys.stderr, flush=True)
+        for k in KINDS:
+            oracle.seed(oracle.GENERATORS[k], seed, 1)  # build the oracle's lazy tables first
+        by_stream = {}
+        for i, s in enumerate(tab["stream"].tolist()):
+            by_stream.setdefault(s, []).append(i)
+        ptrs = []
+        for tk in tickets:
+            done, ptr = rng.rng_server_poll(h, int(tk))
+            assert done and ptr
+            ptrs.append(ptr)
+
+        def check(streams):
+            bad = []
+            for s in map(int, streams):
+                k = s % 3
+                o = oracle.GENERATORS[KINDS[k]]
+                stt = oracle.seed(o, seed + k, 1, first_stream=s // 3)
+                for i in by_stream[s]:
+                    L, d = int(tab["length"][i]), int(tab["dtype"][i])
+                    ref = oracle.generate(o, stt, L, d)[0].view(np.uint32)
+                    got = _read(hip, ptrs[i], L)
+                    if not np.array_equal(got, ref):
+                        bad.append("request %d (stream %d, %s, length %d) differs at %d"
+                                   % (i, s, KINDS[k], L, int(np.argmax(got != ref))))
+                words = rng.rng_state_words(gens[k])
+                if not np.array_equal(np.array(rng.rng_server_read_state(h, s, words), np.uint32), stt[:, 0]):
+                    bad.append("stream %d: final state differs" % s)
+            return bad
+
+        keys = sorted(by_stream)
+        bad = []
+        with concurrent.futures.ThreadPoolExecutor(threads) as ex:
+            for r in ex.map(check, np.array_split(np.array(keys), threads)):
+                bad.extend(r)
+        assert not bad, bad[:5]
+        # streams no request touched keep their seeded state
+        untouched = [s for s in range(0, n_streams, 99991) if s not in by_stream][:8]
+        for s in untouched:
+            k = s % 3
+            words = rng.rng_state_words(gens[k])
+            ref = oracle.seed(oracle.GENERATORS[KINDS[k]], seed + k, 1, first_stream=s // 3)[:, 0]
+            assert np.array_equal(np.array(rng.rng_server_read_state(h, s, words), np.uint32), ref), s
+        for tk in tickets:
+            rng.rng_server_release(h, int(tk))
+    finally:
+        rng.rng_server_destroy(h)
