@@ -164,6 +164,23 @@ int rng_generate_split(int g, const uint32_t *d_state_one, uint64_t total, uint6
                        int t, void *d_out, uint32_t *d_final_state, void *d_workspace,
                        uint64_t workspace_bytes, void *stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): rng_generate_split without a
+ * workspace argument.  The thread states live in a device array of
+ * RNG_SPLIT_NOALLOC_SCRATCH_BYTES that the library holds on every device it
+ * runs on until the process ends; the call itself makes no hipMalloc, hipFree
+ * or other allocating call.  rng_init() must have run on the current device
+ * (it builds the tables and looks up the array's address), else RNG_EINVAL.
+ * A split needs 4 * W * T bytes (W state words, T = ceil(total / C) threads
+ * with work, C = ceil(total / n_threads)); larger splits return RNG_ERANGE
+ * (32 MiB holds 2^20 threads of every generator).  Every call on one device
+ * shares the array and leaves it holding its thread states, so calls that
+ * overlap on one device (other streams, other host threads) race: serialise
+ * them.  Arguments, output and errors otherwise as rng_generate_split. */
+#define RNG_SPLIT_NOALLOC_SCRATCH_BYTES (32u << 20)
+int rng_generate_split_noalloc(int g, const uint32_t *d_state_one, uint64_t total, uint64_t n_threads,
+                               int t, void *d_out, uint32_t *d_final_state, void *stream);
+
 /* Leapfrogging (Sec. II.A.4): the same sequence and output as
  * rng_generate_split, computed the other way round.  With T = min(n_threads,
  * total) threads, thread j emits numbers j, j + T, j + 2T, ... of the serial

@@ -54,6 +54,7 @@ _SIGS = {
     "rng_skip": (_int, [_int, _vp, _u64, _u64, _vp]),
     "rng_split_workspace_bytes": (_int, [_int, _u64, _pu64]),
     "rng_generate_split": (_int, [_int, _vp, _u64, _u64, _int, _vp, _vp, _vp, _u64, _vp]),
+    "rng_generate_split_noalloc": (_int, [_int, _vp, _u64, _u64, _int, _vp, _vp, _vp]),
     "rng_fused_pi": (_int, [_int, _vp, _u64, _u64, _vp, _vp]),
     "rng_calibrate_valu": (_int, [_int, ctypes.POINTER(ctypes.c_double), _vp]),
     "rng_calibrate_store": (_int, [_vp, _u64, _u64, _vp, _u32, _u32, _vp]),
@@ -234,6 +235,15 @@ def rng_generate_split(g, d_state_one, total, n_threads, t, d_out, d_final_state
     return _check(_lib.rng_generate_split(g, _ptr(d_state_one), total, n_threads, t, _ptr(d_out),
                                           _ptr(d_final_state), _ptr(d_workspace), workspace_bytes,
                                           _stream(stream)), "rng_generate_split")
+
+
+RNG_SPLIT_NOALLOC_SCRATCH_BYTES = 32 << 20
+
+
+def rng_generate_split_noalloc(g, d_state_one, total, n_threads, t, d_out, d_final_state, stream=None):
+    return _check(_lib.rng_generate_split_noalloc(g, _ptr(d_state_one), total, n_threads, t, _ptr(d_out),
+                                                  _ptr(d_final_state), _stream(stream)),
+                  "rng_generate_split_noalloc")
 
 
 def rng_leapfrog_workspace_bytes(g, n_threads):

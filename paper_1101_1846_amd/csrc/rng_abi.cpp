@@ -100,6 +100,18 @@ int device_tables(DevTables *out)
     return RNG_OK;
 }
 
+int device_tables_if_ready(DevTables *out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(RNG_ENODEV, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_dev[dev].ready) return fail(RNG_EINVAL, "device %d has no tables yet: call rng_init() on it first", dev);
+    *out = g_dev[dev].tab;
+    return RNG_OK;
+}
+
 int shutdown_tables()
 {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -342,6 +354,62 @@ int check_sizes(uint64_t S, uint64_t N, uint64_t words)
     return RNG_OK;
 }
 
+// Sequence splitting after the argument checks of the entry points: thread
+// states in ws ([W][T] words, ws_bytes available), a radix-16 tree of jumps,
+// then the generation launch(es) and the final state.  Launches only.
+int split_args_check(uint64_t total, uint64_t n_threads, const void *d_out, const uint32_t *d_state_one,
+                     const uint32_t *d_final_state)
+{
+    if (!d_out) return fail(RNG_EINVAL, "NULL output");
+    if (n_threads == 0) return fail(RNG_EINVAL, "n_threads is 0");
+    if (((uintptr_t)d_out & 3) || ((uintptr_t)d_state_one & 3) || ((uintptr_t)d_final_state & 3))
+        return fail(RNG_EINVAL, "misaligned pointer");
+    return check_sizes(1, total, 1);
+}
+
+int split_run(int g, const uint32_t *d_state_one, uint64_t total, uint64_t n_threads, int t, void *d_out,
+              uint32_t *d_final_state, uint32_t *ws, uint64_t ws_bytes, const DevTables &tab, hipStream_t st)
+{
+    const uint64_t C = (total + n_threads - 1) / n_threads;
+    const uint64_t T = (total + C - 1) / C;  // threads with work
+    uint64_t need;
+    if (int rc = split_scratch_bytes(g, total, n_threads, &need)) return rc;
+    if (ws_bytes < need)
+        return fail(RNG_ENOMEM, "workspace %llu bytes < %llu", (unsigned long long)ws_bytes, (unsigned long long)need);
+    int rc = check_launch(dispatch_state_copy(g, d_state_one, 1, 0, ws, T, 0, st), "split: init");
+    if (rc) return rc;
+    // radix-16 tree: level l starts threads [16^l, 16^(l+1)) from threads below 16^l
+    uint64_t far;
+    if (mul_overflows(C, T, &far)) return fail(RNG_ERANGE, "jump distance overflows");
+    for (uint32_t shift = 0; ((uint64_t)1 << shift) < T; shift += 4) {
+        rc = check_launch(dispatch_tree_level(g, ws, T, shift, C, tab, st), "split: tree level");
+        if (rc) return rc;
+    }
+    const uint64_t rem = total - (T - 1) * C;  // samples of the last thread
+    const uint64_t full = rem == C ? T : T - 1;
+    Shape shape = tuned_shape(g, t);
+    if (full) {
+        rc = generate_impl(g, t, ws, T, full, C, d_out, shape, true, st);
+        if (rc) return rc;
+    }
+    if (full < T) {
+        rc = generate_impl(g, t, ws + (T - 1), T, 1, rem, (uint32_t *)d_out + (T - 1) * C, shape, true, st);
+        if (rc) return rc;
+    }
+    return check_launch(dispatch_state_copy(g, ws, T, T - 1, d_final_state, 1, 0, st), "split: final");
+}
+
+// Workspace bytes a split of `total` samples over n_threads threads uses:
+// one state per thread with work.
+int split_scratch_bytes(int g, uint64_t total, uint64_t n_threads, uint64_t *bytes)
+{
+    if (n_threads == 0) return fail(RNG_EINVAL, "n_threads is 0");
+    const uint64_t C = (total + n_threads - 1) / n_threads;
+    const uint64_t T = C ? (total + C - 1) / C : 0;
+    if (mul_overflows(T, (uint64_t)gen_words(g) * 4, bytes)) return fail(RNG_ERANGE, "n_threads too large");
+    return RNG_OK;
+}
+
 }  // namespace rngx
 
 using namespace rngx;
@@ -368,7 +436,8 @@ const char *rng_last_error(void) { return g_last_error.c_str(); }
 int rng_init(void)
 {
     DevTables t;
-    return device_tables(&t);
+    if (int rc = device_tables(&t)) return rc;
+    return scratch_init_current_device();
 }
 
 int rng_shutdown(void) { return shutdown_tables(); }
@@ -477,46 +546,18 @@ int rng_generate_split(int g, const uint32_t *d_state_one, uint64_t total, uint6
                                       (hipStream_t)stream);
         return e == hipSuccess ? RNG_OK : hip_fail(e, "hipMemcpyAsync");
     }
-    if (!d_out || !d_workspace) return fail(RNG_EINVAL, "NULL output or workspace");
-    if (n_threads == 0) return fail(RNG_EINVAL, "n_threads is 0");
-    if (((uintptr_t)d_out & 3) || ((uintptr_t)d_workspace & 255) || ((uintptr_t)d_state_one & 3) ||
-        ((uintptr_t)d_final_state & 3))
-        return fail(RNG_EINVAL, "misaligned pointer");
-    if (int rc = check_sizes(1, total, 1)) return rc;
-    const int W = gen_words(g);
-    const uint64_t C = (total + n_threads - 1) / n_threads;
-    const uint64_t T = (total + C - 1) / C;  // threads with work
+    if (int rc = split_args_check(total, n_threads, d_out, d_state_one, d_final_state)) return rc;
+    if (!d_workspace) return fail(RNG_EINVAL, "NULL workspace");
+    if ((uintptr_t)d_workspace & 255) return fail(RNG_EINVAL, "misaligned pointer");
     uint64_t need;
-    rng_split_workspace_bytes(g, T, &need);
+    if (int rc = split_scratch_bytes(g, total, n_threads, &need)) return rc;
     if (workspace_bytes < need)
         return fail(RNG_ENOMEM, "workspace %llu bytes < %llu", (unsigned long long)workspace_bytes,
                     (unsigned long long)need);
     DevTables tab;
     if (int rc = device_tables(&tab)) return rc;
-    hipStream_t st = (hipStream_t)stream;
-    uint32_t *ws = (uint32_t *)d_workspace;
-    int rc = check_launch(dispatch_state_copy(g, d_state_one, 1, 0, ws, T, 0, st), "split: init");
-    if (rc) return rc;
-    // radix-16 tree: level l starts threads [16^l, 16^(l+1)) from threads below 16^l
-    uint64_t far;
-    if (mul_overflows(C, T, &far)) return fail(RNG_ERANGE, "jump distance overflows");
-    for (uint32_t shift = 0; ((uint64_t)1 << shift) < T; shift += 4) {
-        rc = check_launch(dispatch_tree_level(g, ws, T, shift, C, tab, st), "split: tree level");
-        if (rc) return rc;
-    }
-    const uint64_t rem = total - (T - 1) * C;  // samples of the last thread
-    const uint64_t full = rem == C ? T : T - 1;
-    Shape shape = tuned_shape(g, t);
-    if (full) {
-        rc = generate_impl(g, t, ws, T, full, C, d_out, shape, true, st);
-        if (rc) return rc;
-    }
-    if (full < T) {
-        rc = generate_impl(g, t, ws + (T - 1), T, 1, rem, (uint32_t *)d_out + (T - 1) * C, shape, true, st);
-        if (rc) return rc;
-    }
-    (void)W;
-    return check_launch(dispatch_state_copy(g, ws, T, T - 1, d_final_state, 1, 0, st), "split: final");
+    return split_run(g, d_state_one, total, n_threads, t, d_out, d_final_state, (uint32_t *)d_workspace,
+                     workspace_bytes, tab, (hipStream_t)stream);
 }
 
 int rng_fused_pi(int g, uint32_t *d_state, uint64_t n_streams, uint64_t n, uint64_t *d_count, void *stream)

@@ -43,6 +43,19 @@ int dispatch_state_copy(int g, const uint32_t *src, uint64_t ss, uint64_t si, ui
 int generate_few(int g, int dt, uint32_t *d_state, uint64_t ld, uint64_t S, uint64_t N, uint64_t C, uint64_t P,
                  void *d_out, const DevTables &tab, hipStream_t st);
 
+// Tables of the current device only if they exist already (never allocates).
+int device_tables_if_ready(DevTables *out);
+// Looks up, once per device, the address of the allocation-free entry
+// point's scratch array on the current device (called by rng_init).
+int scratch_init_current_device();
+// Sequence splitting: argument checks, the workspace a split needs, and the
+// launches themselves (thread states in ws, [W][T] words).
+int split_args_check(uint64_t total, uint64_t n_threads, const void *d_out, const uint32_t *d_state_one,
+                     const uint32_t *d_final_state);
+int split_scratch_bytes(int g, uint64_t total, uint64_t n_threads, uint64_t *bytes);
+int split_run(int g, const uint32_t *d_state_one, uint64_t total, uint64_t n_threads, int t, void *d_out,
+              uint32_t *d_final_state, uint32_t *ws, uint64_t ws_bytes, const DevTables &tab, hipStream_t st);
+
 // rng_batch_set without the check that no two requests share a state (for
 // callers that keep one request per state).
 int batch_set_distinct(rng_batch_t *h, const rng_request_t *reqs, uint32_t n);

@@ -142,6 +142,25 @@ def test_split_validation(rng):
     del small
 
 
+def test_split_noalloc_validation(rng):
+    """The allocation-free split rejects bad arguments, and splits whose thread
+    states exceed its scratch array, before any device call."""
+    L = rng.raw()
+    big = 1 << 40
+    assert L.rng_generate_split_noalloc(9, big, 100, 4, 0, big, big, None) == rng.RNG_EINVAL
+    assert L.rng_generate_split_noalloc(rng.RNG_MWC32, big, 100, 4, 7, big, big, None) == rng.RNG_EINVAL
+    assert L.rng_generate_split_noalloc(rng.RNG_MWC32, None, 100, 4, 0, big, big, None) == rng.RNG_EINVAL
+    assert L.rng_generate_split_noalloc(rng.RNG_MWC32, big, 100, 0, 0, big, big, None) == rng.RNG_EINVAL
+    assert L.rng_generate_split_noalloc(rng.RNG_MWC32, big, 100, 4, 0, None, big, None) == rng.RNG_EINVAL
+    assert L.rng_generate_split_noalloc(rng.RNG_MWC32, big + 2, 100, 4, 0, big, big, None) == rng.RNG_EINVAL
+    # XS256: 32 bytes of state per thread, 2^21 threads need 64 MiB > 32 MiB
+    assert rng.RNG_SPLIT_NOALLOC_SCRATCH_BYTES == 32 << 20
+    assert L.rng_generate_split_noalloc(rng.RNG_XS256, big, 1 << 22, 1 << 21, 0, big, big, None) == rng.RNG_ERANGE
+    assert L.rng_generate_split_noalloc(rng.RNG_MWC32, big, 1 << 23, 1 << 23, 0, big, big, None) == rng.RNG_ERANGE
+    hdr = open(os.path.join(ROOT, "include", "rng.h")).read()
+    assert "#define RNG_SPLIT_NOALLOC_SCRATCH_BYTES (32u << 20)" in hdr
+
+
 def test_product_never_imports_the_oracle():
     pkg = os.path.join(ROOT, "paper_1101_1846_amd")
     for dirpath, _, files in os.walk(pkg):
