@@ -294,10 +294,10 @@ int rng_batch_launch(rng_batch_t *h, void *stream);
  * host time against 2.6 us per direct launch, so the direct launches give
  * the lower latency. */
 int rng_batch_set_graph(rng_batch_t *h, int use_graph);
-/* Persistent-kernel shape: wg lanes per workgroup and unroll (samples per
- * generation step), one of the built pairs: wg 64, 128, 256 or 512 with
- * unroll 8, and unroll 1, 2, 4 or 16 with wg 256 (other pairs RNG_EINVAL);
- * and chunk length C (a multiple of 64).  0 keeps the current value.  chunk = RNG_BATCH_CHUNK_AUTO lets every plan
+/* Persistent-kernel shape: wg lanes per workgroup in {64, 128, 256, 512,
+ * 1024} and unroll (samples per generation step) in {1, 2, 4, 8, 16}, every
+ * pair built (others RNG_EINVAL; 1024-lane workgroups stage 32-sample LDS
+ * tiles, the others 64); and chunk length C (a multiple of 64).  0 keeps the current value.  chunk = RNG_BATCH_CHUNK_AUTO lets every plan
  * choose C: the power of two in [64, 4096] that cuts the batch into about
  * 2^17 chunks (as many 64-chunk tiles as the device holds waves), so that
  * small batches still spread over the device; the workspace is sized for
@@ -308,9 +308,9 @@ int rng_batch_set_graph(rng_batch_t *h, int use_graph);
 int rng_batch_set_shape(rng_batch_t *h, uint32_t wg, uint32_t unroll, uint32_t chunk);
 /* The current shape; chunk reads RNG_BATCH_CHUNK_AUTO in automatic mode. */
 int rng_batch_get_shape(rng_batch_t *h, uint32_t *wg, uint32_t *unroll, uint32_t *chunk);
-/* Time the planned batch under every persistent-kernel shape (wg x unroll)
- * and chunk length in {512, 1024, 2048, 4096}, reps launches each, and keep
- * the fastest.  Every trial launch runs the batch, so the request states
+/* Time the planned batch under every persistent-kernel shape (the 25 pairs
+ * wg x unroll) and chunk length in {512, 1024, 2048, 4096}, reps launches
+ * each after one warm-up launch, and keep the fastest.  Every trial launch runs the batch, so the request states
  * advance and the outputs are overwritten. */
 int rng_batch_autotune(rng_batch_t *h, uint32_t reps, uint32_t *best_wg, uint32_t *best_unroll,
                        uint32_t *best_chunk, float *best_us, void *stream);

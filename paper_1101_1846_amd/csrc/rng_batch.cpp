@@ -497,7 +497,14 @@ int rng_batch_autotune(rng_batch_t *h, uint32_t reps, uint32_t *best_wg, uint32_
         std::lock_guard<std::mutex> lk(h->mu);
         if (h->last.empty()) return fail(RNG_EINVAL, "no planned batch to tune on");
     }
-    static const uint32_t shapes[][2] = {{64, 8}, {128, 8}, {256, 8}, {512, 8}, {256, 1}, {256, 2}, {256, 4}, {256, 16}};
+    // every built shape: workgroups of 64..1024 lanes x unroll 1..16 (the
+    // paper chose its block size by occupancy and unrolled its main loop)
+    static const uint32_t wgs[] = {64, 128, 256, 512, 1024}, unrolls[] = {1, 2, 4, 8, 16};
+    uint32_t shapes[25][2];
+    for (int i = 0; i < 25; ++i) {
+        shapes[i][0] = wgs[i / 5];
+        shapes[i][1] = unrolls[i % 5];
+    }
     static const uint32_t chunks[] = {512, 1024, 2048, 4096};
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t e0, e1;

@@ -129,8 +129,7 @@ def test_batch_alone_equals_in_mix(rng, torch, oracle):
         rng.rng_batch_destroy(h)
 
 
-@pytest.mark.parametrize("shape", [(64, 8), (128, 8), (256, 8), (512, 8), (256, 1), (256, 2), (256, 4),
-                                   (256, 16)])
+@pytest.mark.parametrize("shape", [(wg, u) for wg in (64, 128, 256, 512, 1024) for u in (1, 2, 4, 8, 16)])
 def test_batch_every_shape(rng, torch, oracle, shape):
     m = Mix(rng, torch, oracle, 80, seed=3, max_len=6000)
     h = rng.rng_batch_create(100, 1 << 20)

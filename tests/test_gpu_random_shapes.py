@@ -154,8 +154,7 @@ def test_random_fused_and_fold(rng, torch, oracle, case):
 def _batch_cases(n, seed):
     r = np.random.default_rng(seed)
     chunks = (0xFFFFFFFF, 64, 128, 192, 256, 1024, 4096)  # RNG_BATCH_CHUNK_AUTO first
-    # the batch kernel's built shapes: a workgroup sweep at unroll 8 and an unroll sweep at 256 lanes
-    shapes = [(64, 8), (128, 8), (256, 8), (512, 8), (256, 1), (256, 2), (256, 4), (256, 16)]
+    shapes = SHAPES  # every (workgroup, unroll) pair the batch kernel is built for
     return [(i, int(r.integers(1, 300)), _logu(r, 1 << 16), shapes[r.integers(len(shapes))],
              chunks[r.integers(len(chunks))]) for i in range(n)]
 
