@@ -24,11 +24,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0           # MI355X HBM3E, 8 TB/s
-# 32-bit integer VALU issues at the FP32-vector rate: 157.3 TFLOP/s counts an
-# FMA as 2 operations, so 78.6e12 lane-operations/s (256 CUs x 2.4 GHz x 128).
-VALU_PEAK_OPS = 157.3e12 / 2
+# Full-rate 32-bit integer VALU: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz.
+# The 157.3 TFLOP/s FP32 figure counts packed FP32 FMAs (2 FLOPs x 2 per lane),
+# which integer work cannot use.
+VALU_INT32_SPEC = 256 * 4 * 16 * 2.4e9
+# Abstract operations per fused sample (eq. (9)): KISS 20 (MWC1616 10, xorshift32
+# 6, LCG 2, combine 2) and about 4 for the pair test.
 FUSED_OPS_PER_SAMPLE = 24
-FUSED_VALU_PER_SAMPLE = 19.5     # 156 VALU instructions per 8 samples in the compiled loop
 
 S_BULK, N_BULK = 1 << 20, 256
 STEP_GENS = ["XS256", "XS32", "KISS"]
@@ -48,7 +50,8 @@ def parse():
                    help="run one side workload alone and print its JSON record")
     p.add_argument("--profile", metavar="GEN_DTYPE",
                    help="counter-collection mode: a 1 GiB device copy (calibration) then 3 launches of "
-                        "one step kernel, e.g. XS256_u32; prints nothing else")
+                        "one step kernel, e.g. XS256_u32; or 'fused' (fused pi and its VALU calibration); "
+                        "prints nothing else")
     return p.parse_args()
 
 
@@ -371,13 +374,17 @@ def split_workload(torch, R, dev):
         ws = torch.empty(wsb // 4, dtype=torch.int32, device=dev)
         ms = _time(torch, lambda: R.rng_generate_split(g, s1, total, T, R.RNG_U32, o, fin, ws, wsb), 5)
         # the generation phase alone: the same launch over T states of T x (total / T) samples
-        st = torch.empty((W, T), dtype=torch.int32, device=dev)
-        R.rng_seed(g, 2, 0, T, st)
-        gen_ms = _time(torch, lambda: R.rng_generate(g, st, T, total // T, R.RNG_U32, o), 5)
+        C, rows = total // T, T
+        st = torch.empty((W, rows), dtype=torch.int32, device=dev)
+        R.rng_seed(g, 2, 0, rows, st)
+        gen_ms = _time(torch, lambda: R.rng_generate(g, st, rows, C, R.RNG_U32, o), 5)
+        gen_bytes = 4 * rows * C + 2 * 4 * W * rows
         res["split_2^30_%s" % name] = {"ms": round(ms, 3),
                                        "GSamples_s": round(total / (ms * 1e-3) / 1e9, 1),
                                        "GB_s": round(4 * total / (ms * 1e-3) / 1e9, 1),
+                                       "samples_per_thread": C,
                                        "generation_ms": round(gen_ms, 3),
+                                       "generation_GB_s": round(gen_bytes / (gen_ms * 1e-3) / 1e9, 1),
                                        "setup_ms": round(max(ms - gen_ms, 0.0), 3)}
         del ws, st
     # jump-ahead alone: every one of 2^20 states skipped by one 64-bit distance
@@ -483,7 +490,11 @@ def placement_workload(torch, R, dev):
 
 
 def fused_workload(torch, R, dev):
-    """Fused consumer over 2^34 KISS samples (no stores: integer-VALU bound)."""
+    """Fused consumer over 2^34 KISS samples (no stores: integer-VALU bound),
+    held against the measured ceiling of its own instruction mix (the same
+    loop body on four independent streams per lane, rng_calibrate_valu op 3).
+    VALU instructions per sample come from SQ_INSTS_VALU counter runs on the
+    current kernel sources (profiles/valu.json), else stay null."""
     res = {}
     g = R.RNG_KISS
     S, N = 1 << 20, 1 << 14
@@ -493,18 +504,25 @@ def fused_workload(torch, R, dev):
     ms = _time(torch, lambda: R.rng_fused_pi(g, st, S, N, cnt), 5)
     rate = S * N / (ms * 1e-3)
     calib = {name: R.rng_calibrate_valu(op) for op, name in enumerate(("add_xor", "mad_u24", "mul_lo"))}
-    res["fused_pi_kiss_2^34"] = {
-        "ms": round(ms, 3), "GSamples_s": round(rate / 1e9, 1),
-        # abstract operations per sample (eq. (9)): KISS 20 (MWC1616 10, xorshift32 6, LCG 2, combine 2)
-        # + 4 per sample for the pair test (shift, square, add, compare, count)
-        "roofline": {"kernel": "k_fused_pi<KISS>", "bound": "alu", "unit": "Gop/s",
-                     "achieved": round(rate * FUSED_OPS_PER_SAMPLE / 1e9, 1),
-                     "peak": round(VALU_PEAK_OPS / 1e9, 1),
-                     "frac": round(rate * FUSED_OPS_PER_SAMPLE / VALU_PEAK_OPS, 4),
-                     "ops_per_sample": FUSED_OPS_PER_SAMPLE,
-                     "valu_instructions_per_sample": FUSED_VALU_PER_SAMPLE,
-                     "valu_lane_instructions_per_s": round(rate * FUSED_VALU_PER_SAMPLE / 1e9, 1),
-                     "measured_valu_peak_lane_ops_per_s": {k: round(v / 1e9, 1) for k, v in calib.items()}}}
+    mix = max(R.rng_calibrate_valu(3) for _ in range(3))  # lane-samples/s of the fused loop's mix
+    vps = measured_valu()
+    fv, cv = (vps or {}).get("fused_valu_per_sample"), (vps or {}).get("calib_valu_per_sample")
+    roof = {"kernel": "k_fused_pi<KISS>", "bound": "alu", "unit": "GSamples/s",
+            "achieved": round(rate / 1e9, 1), "peak": round(mix / 1e9, 1), "frac": round(rate / mix, 4),
+            "peak_kind": "measured: the same loop body on 4 independent streams per lane (rng_calibrate_valu op 3)",
+            "abstract_ops_per_sample": FUSED_OPS_PER_SAMPLE,
+            "abstract_Gop_s": round(rate * FUSED_OPS_PER_SAMPLE / 1e9, 1),
+            "valu_instructions_per_sample": fv, "calib_valu_instructions_per_sample": cv,
+            "int32_spec_lane_ops_per_s": VALU_INT32_SPEC,
+            "measured_single_class_lane_ops_per_s": {k: round(v / 1e9, 1) for k, v in calib.items()}}
+    if fv and cv:
+        peak_instr = mix * cv  # lane-instructions/s the mix sustains
+        roof.update({"valu_lane_instructions_per_s": round(rate * fv / 1e9, 1),
+                     "peak_valu_lane_instructions_per_s": round(peak_instr / 1e9, 1),
+                     "frac_valu_instructions": round(rate * fv / peak_instr, 4),
+                     "frac_abstract_ops": round(rate * FUSED_OPS_PER_SAMPLE / peak_instr, 4),
+                     "frac_of_int32_spec": round(rate * fv / VALU_INT32_SPEC, 4)})
+    res["fused_pi_kiss_2^34"] = {"ms": round(ms, 3), "GSamples_s": round(rate / 1e9, 1), "roofline": roof}
     torch.cuda.empty_cache()
     return res
 
@@ -724,7 +742,8 @@ def cpu_baseline(seconds):
 
 
 KERNEL_SOURCES = ["paper_1101_1846_amd/csrc/rng_device.hpp", "paper_1101_1846_amd/csrc/rng_kernels.hpp",
-                  "paper_1101_1846_amd/csrc/rng_internal.hpp", "include/rng_inline.hpp"]
+                  "paper_1101_1846_amd/csrc/rng_internal.hpp", "include/rng_inline.hpp",
+                  "paper_1101_1846_amd/csrc/rng_calib.hip"]
 
 
 def kernel_source_sha():
@@ -751,10 +770,33 @@ def measured_traffic(key):
     return ent.get("hbm_bytes_per_launch")
 
 
+def measured_valu():
+    """VALU instructions per sample of the fused kernel and of its calibration
+    loop from the committed counter runs (profiles/valu.json), or None when
+    missing or taken on other kernel sources."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "valu.json")) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    return rec if rec.get("kernel_source_sha") == kernel_source_sha() else None
+
+
 def profile_mode(torch, R, dev, states, out, key):
     """Launch sequence for the counter runs: a plain 1 GiB device-to-device copy
     (its FETCH_SIZE and WRITE_SIZE calibrate the counters), then three launches
-    of the chosen step kernel."""
+    of the chosen step kernel; key "fused": one fused pi launch over 2^34 KISS
+    samples and one launch of its calibration loop (SQ_INSTS_VALU runs)."""
+    if key == "fused":
+        g, S, N = R.RNG_KISS, 1 << 20, 1 << 14
+        st = torch.empty((6, S), dtype=torch.int32, device=dev)
+        R.rng_seed(g, 6, 0, S, st)
+        cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+        R.rng_fused_pi(g, st, S, N, cnt)
+        R.rng_calibrate_valu(3)
+        torch.cuda.synchronize()
+        print("profile launches done: k_fused_pi<KISS> 2^20 x 2^14, k_valu_fused x 4", flush=True)
+        return
     name, d = key.split("_")
     n = 1 << 28
     a = torch.ones(n, dtype=torch.int32, device=dev)

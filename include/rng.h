@@ -108,7 +108,10 @@ int rng_generate(int g, uint32_t *d_state, uint64_t n_streams, uint64_t n, int t
 
 /* Same, with an explicit launch shape: wg in {64,128,256,512,1024} lanes per
  * workgroup and unroll in {1,2,4,8,16} samples per generation-loop step.
- * rng_generate uses the autotuned shape when one is loaded, else a default. */
+ * rng_generate uses the autotuned shape when one is loaded, else a default;
+ * for XS256 rows of whole multiples of 4 KiB (n % 1024 == 0) it takes at
+ * least 512 lanes, which generate each row as four jumped chunks so that
+ * concurrent writes spread over four column slots. */
 int rng_generate_ex(int g, uint32_t *d_state, uint64_t n_streams, uint64_t n, int t,
                     void *d_out, uint32_t wg, uint32_t unroll, void *stream);
 
@@ -125,9 +128,13 @@ int rng_autotune(int g, int t, uint64_t n_streams, uint64_t n, uint32_t *d_state
 
 /* Measured 32-bit integer VALU rate of the current device in lane-operations
  * per second, for op 0 (add + xor), 1 (24-bit multiply-add), 2 (32-bit
- * multiply low): eight independent chains per lane on every SIMD.  The
- * paper derived its integer peak as a third of the FP rate (Sec. V) and
- * measured only bandwidth; this measures the integer rate.  Synchronous. */
+ * multiply low): eight independent chains per lane on every SIMD.  op 3
+ * returns lane-samples per second of the fused consumer's own loop body
+ * (rng_fused_pi's KISS pairs and exact quarter-circle test) on four
+ * independent streams per lane: the ceiling of that instruction mix when no
+ * instruction waits on the one before.  The paper derived its integer peak
+ * as a third of the FP rate (Sec. V) and measured only bandwidth; this
+ * measures the integer rate.  Synchronous. */
 int rng_calibrate_valu(int op, double *lane_ops_per_s, void *stream);
 
 /* Achievable write rate of the bulk store schedule (Sec. V measured its

@@ -151,6 +151,16 @@ Shape tuned_shape(int g, int dt)
     return s;
 }
 
+// The shape rng_generate uses for n samples per stream: the tuned one, except
+// that XS256 rows of whole 4 KiB multiples take 512-lane workgroups (their
+// four-chunk path; the tuned shape is measured on other row lengths).
+Shape row_shape(int g, int dt, uint64_t n)
+{
+    Shape s = tuned_shape(g, dt);
+    if (g == RNG_XS256 && n % 1024 == 0 && s.wg < 512) s.wg = 512;
+    return s;
+}
+
 void set_tuned_shape(int g, int dt, Shape s)
 {
     std::lock_guard<std::mutex> lk(g_shape_mu);
@@ -328,6 +338,20 @@ int generate_impl(int g, int dt, uint32_t *d_state, uint64_t ld, uint64_t S, uin
         if (P > 1) return check_launch(generate_few(g, dt, d_state, ld, S, N, c, P, d_out, tab, st), "rng_generate");
     }
     choose_chunks(g, S, N, kGenTile, &a.C, &a.P, kGenLanes);
+    // XS256 rows of whole 4 KiB multiples (no rotated order: a row would need
+    // a 256 x 256 jump inside the write stream): four chunks per stream, each
+    // jumped once at its start, before any store (one table product per
+    // nonzero hexadecimal digit of j N / 4: one for N = 1024), so that the
+    // waves of a group write four different column slots at once.  Only with
+    // workgroups of 8+ waves: they hold all four chunks of their groups and
+    // write the states back themselves, and their 32-sample tiles measured
+    // faster here than 4-wave workgroups with 128-sample tiles (XS256 2^20 x
+    // 1024: 832-867 us at 512 lanes against 1090-1127 at 256 and 887-949 for
+    // the plain order).
+    if (g == RNG_XS256 && staged && a.P == 1 && a.vec4 && S % 64 == 0 && N % 1024 == 0 && shape.wg >= 512) {
+        a.C = N / kXs256RowChunks;
+        a.P = kXs256RowChunks;
+    }
     // rows of whole 4 KiB multiples on the resident schedule: rotated tile order
     if (g != RNG_XS256 && staged && a.P == 1 && a.vec4 && S % 64 == 0 && N % 1024 == 0) {
         a.rot = 1;
@@ -387,9 +411,16 @@ int split_run(int g, const uint32_t *d_state_one, uint64_t total, uint64_t n_thr
     }
     const uint64_t rem = total - (T - 1) * C;  // samples of the last thread
     const uint64_t full = rem == C ? T : T - 1;
-    Shape shape = tuned_shape(g, t);
-    if (full) {
-        rc = generate_impl(g, t, ws, T, full, C, d_out, shape, true, st);
+    Shape shape = row_shape(g, t, C);
+    // whole 64-thread groups in one launch (the resident schedule needs them),
+    // the rest of the full threads in a second
+    const uint64_t full64 = full / 64 * 64;
+    if (full64) {
+        rc = generate_impl(g, t, ws, T, full64, C, d_out, shape, true, st);
+        if (rc) return rc;
+    }
+    if (full > full64) {
+        rc = generate_impl(g, t, ws + full64, T, full - full64, C, (uint32_t *)d_out + full64 * C, shape, true, st);
         if (rc) return rc;
     }
     if (full < T) {
@@ -506,7 +537,7 @@ int rng_generate(int g, uint32_t *d_state, uint64_t n_streams, uint64_t n, int t
 {
     if (check_gen(g)) return RNG_EINVAL;
     if (t != RNG_U32 && t != RNG_F32) return fail(RNG_EINVAL, "unknown dtype %d", t);
-    Shape s = tuned_shape(g, t);
+    Shape s = row_shape(g, t, n);
     return rng_generate_ex(g, d_state, n_streams, n, t, d_out, s.wg, s.unroll, stream);
 }
 

@@ -21,6 +21,7 @@ int device_tables(DevTables *out);
 int gen_words(int g);
 bool valid_shape(uint32_t wg, uint32_t unroll);
 Shape tuned_shape(int g, int dt);
+Shape row_shape(int g, int dt, uint64_t n);
 void set_tuned_shape(int g, int dt, Shape s);
 // Chunks per stream: the largest power of two p with S p <= target_lanes and
 // chunks of at least the generator's minimum length.

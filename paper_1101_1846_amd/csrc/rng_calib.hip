@@ -8,6 +8,7 @@
 
 #include "rng.h"
 #include "rng_abi_internal.hpp"
+#include "rng_kernels.hpp"
 
 namespace rngx {
 
@@ -32,13 +33,48 @@ __global__ __launch_bounds__(256) void k_valu(uint32_t *out, uint32_t iters, uin
     if (r == 0x9E3779B9u) out[blockIdx.x * 256 + threadIdx.x] = r;  // keeps the chains alive
 }
 
+// OP 3: the fused consumer's own loop body (a KISS number pair and the exact
+// quarter-circle test, eight numbers per stream and iteration, as
+// k_fused_pi runs it) on NS independent streams per lane, interleaved, so
+// that no instruction waits for the previous one's result: the rate the
+// VALU sustains for that instruction mix.  Returns lane-samples per second.
+template <int NS>
+__global__ __launch_bounds__(256) void k_valu_fused(uint32_t *out, uint32_t iters, uint32_t seed)
+{
+    rng_inline::KISS g[NS];
+    const uint32_t id = blockIdx.x * 256 + threadIdx.x;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        g[s].z = seed ^ (id * 2654435761u + s) | 1u;
+        g[s].w = (id + 77u * s) | 1u;
+        g[s].jsr = id * 40503u + s + 1u;
+        g[s].jcong = id + s;
+        g[s].a1 = 18000u + 2u * s;  // any 16-bit multipliers: only the instruction mix matters
+        g[s].a2 = 30903u + 2u * s;
+    }
+    uint32_t cnt = 0;
+    for (uint32_t it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int u = 0; u < 8; u += 2) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const uint32_t x = g[s].next() >> 8, y = g[s].next() >> 8;
+                cnt += in_quarter_circle(x, y);
+            }
+        }
+    }
+    if (cnt == 0x9E3779B9u) out[id] = cnt;  // keeps the chains alive
+}
+
+constexpr int kFusedCalibStreams = 4;
+
 }  // namespace rngx
 
 using namespace rngx;
 
 extern "C" int rng_calibrate_valu(int op, double *lane_ops_per_s, void *stream)
 {
-    if (!lane_ops_per_s || op < 0 || op > 2) return fail(RNG_EINVAL, "bad argument");
+    if (!lane_ops_per_s || op < 0 || op > 3) return fail(RNG_EINVAL, "bad argument");
     DevTables tab;
     if (int rc = device_tables(&tab)) return rc;
     int dev = 0, cus = 256;
@@ -57,7 +93,9 @@ extern "C" int rng_calibrate_valu(int op, double *lane_ops_per_s, void *stream)
     auto launch = [&]() {
         if (op == 0) hipLaunchKernelGGL(k_valu<0>, dim3(blocks), dim3(256), 0, st, out, iters, 0x9E3779B9u, 0x7F4A7C15u);
         else if (op == 1) hipLaunchKernelGGL(k_valu<1>, dim3(blocks), dim3(256), 0, st, out, iters, 69069u, 1234567u);
-        else hipLaunchKernelGGL(k_valu<2>, dim3(blocks), dim3(256), 0, st, out, iters, 69069u, 0u);
+        else if (op == 2) hipLaunchKernelGGL(k_valu<2>, dim3(blocks), dim3(256), 0, st, out, iters, 69069u, 0u);
+        else hipLaunchKernelGGL(k_valu_fused<kFusedCalibStreams>, dim3(blocks), dim3(256), 0, st, out, iters / 64,
+                                0x2545F491u);
         return hipGetLastError();
     };
     if (!rc && (e = launch()) != hipSuccess) rc = hip_fail(e, "launch");
@@ -74,6 +112,10 @@ extern "C" int rng_calibrate_valu(int op, double *lane_ops_per_s, void *stream)
     if (e1) (void)hipEventDestroy(e1);
     (void)hipFree(out);
     if (rc) return rc;
+    if (op == 3) {  // lane-samples: 8 numbers per stream and iteration
+        *lane_ops_per_s = (double)blocks * 256 * (iters / 64) * 8 * kFusedCalibStreams * 3 / (ms * 1e-3);
+        return RNG_OK;
+    }
     const double ops_per_step = op == 0 ? 2.0 : 1.0;
     *lane_ops_per_s = (double)blocks * 256 * iters * 8 * ops_per_step * 3 / (ms * 1e-3);
     return RNG_OK;

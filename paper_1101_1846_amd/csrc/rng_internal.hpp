@@ -20,6 +20,11 @@ constexpr int kGenTile = RNGX_GEN_TILE;
 
 constexpr int gen_tile_depth(int wg) { return wg * (kGenTile + 4) * 4 <= 160 * 1024 ? kGenTile : 32; }
 
+// Chunks per row for XS256 rows of whole 4 KiB multiples on 512- and
+// 1024-lane workgroups (measured at 2^20 x 1024: 4 chunks 836 us; 8 chunks,
+// with jumps by multiples of 128 samples, 1244 us or more).
+constexpr uint32_t kXs256RowChunks = 4;
+
 // Staged store schedule: 1 = whole tile at once, 2 = software-pipelined.
 #ifndef RNGX_STORE_MODE
 #define RNGX_STORE_MODE 2

@@ -466,6 +466,19 @@ __global__ __launch_bounds__(WG) void k_generate(GenArgs a)
 }
 
 // ------------------------------------------------------------------ fused pi
+// 1 when i^2 + j^2 < 2^48 for 24-bit i, j (x^2 + y^2 < 1 for the exact FP32
+// uniforms x = i 2^-24, y = j 2^-24): i^2 = hi 2^32 + lo with hi < 2^16, so
+// the 48-bit sum is tested on its high word after the carry.
+__device__ __forceinline__ uint32_t in_quarter_circle(uint32_t x, uint32_t y)
+{
+    const uint64_t px = (uint64_t)x * x, py = (uint64_t)y * y;  // 24 x 24 -> 48 bits
+    const uint32_t xl = (uint32_t)px, xh = (uint32_t)(px >> 32);
+    const uint32_t yl = (uint32_t)py, yh = (uint32_t)(py >> 32);
+    const uint32_t lo = xl + yl;
+    const uint32_t hi = xh + yh + (lo < xl);
+    return hi < 65536u;
+}
+
 // Pairs (u_{2k}, u_{2k+1}) -> i = u >> 8, j = u >> 8; count i^2 + j^2 < 2^48
 // with 24-bit multiplies: i^2 = hi * 2^32 + lo, hi < 2^16.  Chunk lengths are
 // even so that pairs never straddle chunks.
@@ -510,13 +523,8 @@ __global__ __launch_bounds__(WG) void k_fused_pi(FusedArgs a)
     for (uint64_t it = 0; it < full; ++it) {
 #pragma unroll
         for (int u = 0; u < U; u += 2) {
-            uint32_t x = g.next() >> 8, y = g.next() >> 8;
-            uint64_t px = (uint64_t)x * x, py = (uint64_t)y * y;  // 24 x 24 -> 48 bits
-            uint32_t xl = (uint32_t)px, xh = (uint32_t)(px >> 32);
-            uint32_t yl = (uint32_t)py, yh = (uint32_t)(py >> 32);
-            uint32_t lo = xl + yl;
-            uint32_t hi = xh + yh + (lo < xl);
-            cnt += hi < 65536u;
+            const uint32_t x = g.next() >> 8, y = g.next() >> 8;
+            cnt += in_quarter_circle(x, y);
         }
         if ((it & 0xFFFF) == 0xFFFF) { total += cnt; cnt = 0; }
     }

@@ -4,11 +4,15 @@ counters, as short text tables.
 
     python -m paper_1101_1846_amd.prof trace RUN_results.db
     python -m paper_1101_1846_amd.prof pmc FETCH_results.db WRITE_results.db KEY
+    python -m paper_1101_1846_amd.prof valu VALU_results.db KERNEL_SOURCE_SHA
 
 The ``pmc`` form scales each counter by what it reads for the plain 1 GiB
 device-to-device copy that ``bench.py --profile KEY`` launches first (the copy
 moves exactly 2^30 bytes each way), and prints the JSON record that
-``profiles/traffic.json`` keeps for that kernel.
+``profiles/traffic.json`` keeps for that kernel.  The ``valu`` form reads the
+SQ_INSTS_VALU run of ``bench.py --profile fused`` and prints the record that
+``profiles/valu.json`` keeps (VALU instructions per sample of the fused kernel
+and of its calibration loop).
 """
 import json
 import sqlite3
@@ -76,6 +80,32 @@ def pmc_record(fetch_db, write_db, key):
     }
 
 
+# Samples per dispatch of the kernels that `bench.py --profile fused` launches:
+# fused pi over 2^20 streams x 2^14 samples, and the calibration loop's lanes x
+# 64 iterations x 8 samples x 4 streams.
+FUSED_SAMPLES = 1 << 34
+CALIB_SAMPLES_PER_LANE = 64 * 8 * 4
+
+
+def valu_record(db, sha):
+    """VALU instructions per lane-sample of the fused kernel and of its
+    calibration loop, from SQ_INSTS_VALU (wave instructions) x 64 lanes."""
+    per = defaultdict(float)
+    grid = {}
+    for did, name, g, v in _rows(db, "select dispatch_id, kernel_name, grid_size, value from counters_collection "
+                                      "where counter_name = 'SQ_INSTS_VALU' order by dispatch_id"):
+        per[(did, name)] += v
+        grid[(did, name)] = g
+    fused = [v for (d, n), v in per.items() if "k_fused_pi" in n]
+    calib = [(v, grid[(d, n)]) for (d, n), v in per.items() if "k_valu_fused" in n]
+    rec = {"kernel_source_sha": sha,
+           "fused_valu_per_sample": round(sum(fused) / len(fused) * 64 / FUSED_SAMPLES, 3),
+           "calib_valu_per_sample": round(sum(v * 64 / (g * CALIB_SAMPLES_PER_LANE) for v, g in calib) / len(calib), 3),
+           "fused_SQ_INSTS_VALU_per_dispatch": [int(v) for v in fused],
+           "calib_SQ_INSTS_VALU_per_dispatch": [int(v) for v, _ in calib]}
+    return rec
+
+
 def main(argv):
     if not argv:
         raise SystemExit(__doc__)
@@ -84,6 +114,8 @@ def main(argv):
         print(table)
     elif argv[0] == "pmc":
         print(json.dumps({argv[3]: pmc_record(argv[1], argv[2], argv[3])}, indent=1))
+    elif argv[0] == "valu":
+        print(json.dumps(valu_record(argv[1], argv[2]), indent=1))
     else:
         raise SystemExit(__doc__)
 

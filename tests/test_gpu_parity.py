@@ -202,12 +202,15 @@ def test_skip_many_states(rng, torch, oracle, name, k):
 
 @pytest.mark.parametrize("name", GENS)
 @pytest.mark.parametrize("total,threads", [(1, 1), (1000, 1), (1000, 7), (4096 * 7 + 3, 64), (100000, 1000),
-                                          (65536, 65536), (5, 8), (1024 * 192 + 900, 193)])
+                                          (65536, 65536), (5, 8), (1024 * 192 + 900, 193),
+                                          (1024 * 384, 384), (2048 * 64, 64), (1024, 1)])
 def test_split_parity(rng, torch, oracle, name, total, threads):
     """Sequence splitting (Sec. II.A.4): the concatenated thread outputs equal the
     serial sequence of the one logical stream, and the final state matches.
-    1024 * 192 + 900 over 193 threads: 192 full rows of 1024 (whole 4 KiB rows,
-    the rotated tile order where the generator has one) and a 900-sample tail."""
+    1024 * 192 + 900 over 193 threads: 192 full rows of 1024 (whole 4 KiB
+    rows: the rotated tile order, or for XS256 four jumped chunks per row; 128
+    rows in a first launch, 64 in a second) and a 900-sample tail; 1024 * 384
+    over 384 and 2048 * 64 over 64: whole 4 KiB rows only."""
     g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
     st1 = _dev_state(torch, rng, g, 2, 1)
     ws_bytes = rng.rng_split_workspace_bytes(g, threads)
@@ -377,3 +380,22 @@ def test_fold_parity(rng, torch, oracle, name, dt, S, N):
     ref = oracle.generate(o, ref_st, N, t, threads=4).view(np.uint32)
     assert np.array_equal(_host(fold), np.bitwise_xor.reduce(ref, axis=1))
     assert np.array_equal(_host(st), ref_st)
+
+
+@pytest.mark.parametrize("N", [1024, 2048, 3072, 4096])
+@pytest.mark.parametrize("S", [64, 192, 4096])
+@pytest.mark.parametrize("wg", [512, 1024])
+@pytest.mark.parametrize("dt", ["u32", "f32"])
+def test_xs256_whole_4k_rows_as_chunks(rng, torch, oracle, N, S, wg, dt):
+    """XS256 rows of whole 4 KiB multiples on 512- and 1024-lane workgroups run
+    as four jumped chunks per row (chunk c starts c N / 4 samples in); two
+    calls in a row: every sample and the written-back states of both."""
+    g, o, t = rng.RNG_XS256, oracle.XS256, rng.DTYPES[dt]
+    st = _dev_state(torch, rng, g, 31, S)
+    ref_st = oracle.seed(o, 31, S)
+    for _ in range(2):
+        out = torch.empty((S, N), dtype=torch.int32, device="cuda")
+        rng.rng_generate_ex(g, st, S, N, t, out, wg, 4)
+        ref = oracle.generate(o, ref_st, N, t, threads=4).view(np.uint32)
+        assert np.array_equal(_host(out), ref)
+        assert np.array_equal(_host(st), ref_st)
