@@ -33,6 +33,7 @@ VALU_INT32_SPEC = 256 * 4 * 16 * 2.4e9
 FUSED_OPS_PER_SAMPLE = 24
 
 S_BULK, N_BULK = 1 << 20, 256
+TUNE_REPS = 8  # timed launches per shape when the step's launch shapes are autotuned
 STEP_GENS = ["XS256", "XS32", "KISS"]
 STEP_DTYPES = ["u32", "f32"]
 
@@ -50,7 +51,8 @@ def parse():
                    help="run one side workload alone and print its JSON record")
     p.add_argument("--profile", metavar="GEN_DTYPE",
                    help="counter-collection mode: a 1 GiB device copy (calibration) then 3 launches of "
-                        "one step kernel, e.g. XS256_u32; or 'fused' (fused pi and its VALU calibration); "
+                        "one step kernel, e.g. XS256_u32; 'counter' (the layout ceiling's kernel); or 'fused' (fused pi and "
+                        "its VALU calibration); "
                         "prints nothing else")
     return p.parse_args()
 
@@ -97,26 +99,26 @@ def main():
         for name, d in launches:
             g = R.GENERATORS[name]
             scratch = states[name].clone()
-            wg, un, us = R.rng_autotune(g, R.DTYPES[d], S_BULK, N_BULK, scratch, out, 3)
+            wg, un, us = R.rng_autotune(g, R.DTYPES[d], S_BULK, N_BULK, scratch, out, TUNE_REPS)
             tuned["%s_%s" % (name, d)] = {"wg": wg, "unroll": un, "us": round(us, 1)}
             del scratch
         torch.cuda.synchronize()
 
     def step(events=None):
+        # one event at every launch boundary: launch i runs between events[i] and events[i + 1]
+        if events is not None:
+            events[0].record(stream)
         for i, (name, d) in enumerate(launches):
-            if events is not None:
-                events[i][0].record(stream)
             R.rng_generate(R.GENERATORS[name], states[name], S_BULK, N_BULK, R.DTYPES[d], out)
             if events is not None:
-                events[i][1].record(stream)
+                events[i + 1].record(stream)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
 
     K = args.steps
-    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
-           for _ in launches] for _ in range(K)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(launches) + 1)] for _ in range(K)]
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -134,7 +136,7 @@ def main():
     # per-kernel durations from the live events
     per = {}
     for i, (name, d) in enumerate(launches):
-        durs = [ev[k][i][0].elapsed_time(ev[k][i][1]) for k in range(K)]
+        durs = [ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(K)]
         W = R.rng_state_words(R.GENERATORS[name])
         bytes_alg = S_BULK * N_BULK * 4 + 2 * S_BULK * W * 4
         mean_ms = float(np.mean(durs))
@@ -787,6 +789,14 @@ def profile_mode(torch, R, dev, states, out, key):
     (its FETCH_SIZE and WRITE_SIZE calibrate the counters), then three launches
     of the chosen step kernel; key "fused": one fused pi launch over 2^34 KISS
     samples and one launch of its calibration loop (SQ_INSTS_VALU runs)."""
+    if key == "counter":
+        # the layout ceiling's kernel in the step's commonest shape: 3 launches
+        st = torch.zeros(S_BULK, dtype=torch.int32, device=dev)
+        for _ in range(3):
+            R.rng_calibrate_store(st, S_BULK, N_BULK, out, 256, 4)
+        torch.cuda.synchronize()
+        print("profile launches done: 3 x k_generate<counter> 256 x 4", flush=True)
+        return
     if key == "fused":
         g, S, N = R.RNG_KISS, 1 << 20, 1 << 14
         st = torch.empty((6, S), dtype=torch.int32, device=dev)
@@ -798,6 +808,11 @@ def profile_mode(torch, R, dev, states, out, key):
         print("profile launches done: k_fused_pi<KISS> 2^20 x 2^14, k_valu_fused x 4", flush=True)
         return
     name, d = key.split("_")
+    g = R.GENERATORS[name]
+    # the launch shape the timed step uses: the same autotuning first
+    scratch = states[name].clone()
+    R.rng_autotune(g, R.DTYPES[d], S_BULK, N_BULK, scratch, out, TUNE_REPS)
+    del scratch
     n = 1 << 28
     a = torch.ones(n, dtype=torch.int32, device=dev)
     b = torch.empty_like(a)
@@ -805,7 +820,6 @@ def profile_mode(torch, R, dev, states, out, key):
     b.copy_(a)
     torch.cuda.synchronize()
     del a, b
-    g = R.GENERATORS[name]
     for _ in range(3):
         R.rng_generate(g, states[name], S_BULK, N_BULK, R.DTYPES[d], out)
     torch.cuda.synchronize()

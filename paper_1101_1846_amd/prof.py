@@ -5,6 +5,8 @@ counters, as short text tables.
     python -m paper_1101_1846_amd.prof trace RUN_results.db
     python -m paper_1101_1846_amd.prof pmc FETCH_results.db WRITE_results.db KEY
     python -m paper_1101_1846_amd.prof valu VALU_results.db KERNEL_SOURCE_SHA
+    python -m paper_1101_1846_amd.prof counters KERNEL_NAME_PART PASS1_results.db [PASS2_results.db ...]
+    python -m paper_1101_1846_amd.prof steps RUN_results.db BENCH_LINE.json
 
 The ``pmc`` form scales each counter by what it reads for the plain 1 GiB
 device-to-device copy that ``bench.py --profile KEY`` launches first (the copy
@@ -106,6 +108,48 @@ def valu_record(db, sha):
     return rec
 
 
+def counters_table(match, dbs):
+    """Per counter: the mean over the last three dispatches whose kernel name
+    contains `match` (each dispatch's instances summed), from one or more
+    PMC databases."""
+    out = {}
+    for db in dbs:
+        per = defaultdict(lambda: defaultdict(float))
+        for did, name, c, v in _rows(db, "select dispatch_id, kernel_name, counter_name, value "
+                                         "from counters_collection order by dispatch_id"):
+            if match in name:
+                per[did][c] += v
+        last = sorted(per)[-3:]
+        for did in last:
+            for c, v in per[did].items():
+                out.setdefault(c, []).append(v)
+    return {c: sum(v) / len(v) for c, v in out.items()}
+
+
+def step_table(db, bench_line):
+    """The step kernels of a traced `bench.py` run, in the shapes its JSON line
+    names (launch_shapes), averaged over the timed launches only: the last
+    `steps` dispatches of each before the run's first torch fill kernel (the
+    write-ceiling measurement that follows the timed steps).  Beside each, the
+    same run's HIP-event average from the JSON line."""
+    line = json.load(open(bench_line))
+    steps = line["steps"]
+    rows = [(short(n, 10 ** 6), st, dur) for n, st, dur in _rows(db, "select name, start, duration from kernels "
+                                                                       "order by start")]
+    fills = [st for n, st, d in rows if "FillFunctor" in n]
+    t_fill = fills[0] if fills else float("inf")
+    out = ["| kernel | timed launches | trace avg us | trace min us | trace max us | bench event avg us |",
+           "|---|---|---|---|---|---|"]
+    for key, sh in line["launch_shapes"].items():
+        g, d = key.split("_")
+        pat = "k_generate<Gen%s, %d, %d, %d, 128, 2>" % (g, 1 if d == "f32" else 0, sh["wg"], sh["unroll"])
+        durs = [dur / 1000.0 for n, st, dur in rows if pat in n and st < t_fill][-steps:]
+        ev = line["per_kernel"][key]["ms"] * 1e3
+        out.append("| %s | %d | %.2f | %.2f | %.2f | %.2f |" % (pat, len(durs), sum(durs) / len(durs), min(durs),
+                                                              max(durs), ev))
+    return "\n".join(out)
+
+
 def main(argv):
     if not argv:
         raise SystemExit(__doc__)
@@ -114,6 +158,11 @@ def main(argv):
         print(table)
     elif argv[0] == "pmc":
         print(json.dumps({argv[3]: pmc_record(argv[1], argv[2], argv[3])}, indent=1))
+    elif argv[0] == "steps":
+        print(step_table(argv[1], argv[2]))
+    elif argv[0] == "counters":
+        for c, v in sorted(counters_table(argv[1], argv[2:]).items()):
+            print("| %s | %.4g |" % (c, v))
     elif argv[0] == "valu":
         print(json.dumps(valu_record(argv[1], argv[2]), indent=1))
     else:
