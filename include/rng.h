@@ -130,9 +130,9 @@ int rng_autotune(int g, int t, uint64_t n_streams, uint64_t n, uint32_t *d_state
  * per second, for op 0 (add + xor), 1 (24-bit multiply-add), 2 (32-bit
  * multiply low): eight independent chains per lane on every SIMD.  op 3
  * returns lane-samples per second of the fused consumer's own loop body
- * (rng_fused_pi's KISS pairs and exact quarter-circle test) on four
- * independent streams per lane: the ceiling of that instruction mix when no
- * instruction waits on the one before.  The paper derived its integer peak
+ * (rng_fused_pi's KISS pairs and exact quarter-circle test), the fastest of
+ * 1, 2, 4 and 8 independent streams per lane interleaved: the ceiling of
+ * that instruction mix.  The paper derived its integer peak
  * as a third of the FP rate (Sec. V) and measured only bandwidth; this
  * measures the integer rate.  Synchronous. */
 int rng_calibrate_valu(int op, double *lane_ops_per_s, void *stream);

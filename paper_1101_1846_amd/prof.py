@@ -83,10 +83,10 @@ def pmc_record(fetch_db, write_db, key):
 
 
 # Samples per dispatch of the kernels that `bench.py --profile fused` launches:
-# fused pi over 2^20 streams x 2^14 samples, and the calibration loop's lanes x
-# 64 iterations x 8 samples x 4 streams.
+# fused pi over 2^20 streams x 2^14 samples, and the calibration loop
+# k_valu_fused<NS>: its lanes x 64 iterations x 8 samples x NS streams.
 FUSED_SAMPLES = 1 << 34
-CALIB_SAMPLES_PER_LANE = 64 * 8 * 4
+CALIB_SAMPLES_PER_LANE_PER_STREAM = 64 * 8
 
 
 def valu_record(db, sha):
@@ -99,13 +99,17 @@ def valu_record(db, sha):
         per[(did, name)] += v
         grid[(did, name)] = g
     fused = [v for (d, n), v in per.items() if "k_fused_pi" in n]
-    calib = [(v, grid[(d, n)]) for (d, n), v in per.items() if "k_valu_fused" in n]
-    rec = {"kernel_source_sha": sha,
-           "fused_valu_per_sample": round(sum(fused) / len(fused) * 64 / FUSED_SAMPLES, 3),
-           "calib_valu_per_sample": round(sum(v * 64 / (g * CALIB_SAMPLES_PER_LANE) for v, g in calib) / len(calib), 3),
-           "fused_SQ_INSTS_VALU_per_dispatch": [int(v) for v in fused],
-           "calib_SQ_INSTS_VALU_per_dispatch": [int(v) for v, _ in calib]}
-    return rec
+    calib = defaultdict(list)  # streams per lane -> VALU instructions per lane-sample, per dispatch
+    for (d, n), v in per.items():
+        if "k_valu_fused<" in n:
+            ns = int(n.split("k_valu_fused<")[1].split(">")[0])
+            calib[ns].append(v * 64 / (grid[(d, n)] * CALIB_SAMPLES_PER_LANE_PER_STREAM * ns))
+    per_ns = {ns: round(sum(v) / len(v), 3) for ns, v in sorted(calib.items())}
+    return {"kernel_source_sha": sha,
+            "fused_valu_per_sample": round(sum(fused) / len(fused) * 64 / FUSED_SAMPLES, 3),
+            "calib_valu_per_sample": round(sum(per_ns.values()) / len(per_ns), 3),
+            "calib_valu_per_sample_by_streams_per_lane": per_ns,
+            "fused_SQ_INSTS_VALU_per_dispatch": [int(v) for v in fused]}
 
 
 def counters_table(match, dbs):

@@ -35,3 +35,16 @@ def test_calibrate_store_pattern(rng, torch, S, N, shape):
     assert np.array_equal(got, ref.astype(np.uint32))
     fin = st.cpu().numpy().view(np.uint32)
     assert np.array_equal(fin, ((st0.astype(np.uint64) + N) & 0xFFFFFFFF).astype(np.uint32))
+
+
+def test_calibrate_valu_rates(rng):
+    """Every calibration returns a positive rate below a loose physical bound
+    (4 x the 16-lane int32 issue rate of 256 CUs x 4 SIMDs at 2.4 GHz); the
+    fused mix (op 3) in lane-samples per second at 15-25 VALU instructions per
+    sample stays below that bound divided by 15."""
+    bound = 4 * 256 * 4 * 16 * 2.4e9
+    for op in (0, 1, 2):
+        r = rng.rng_calibrate_valu(op)
+        assert 0 < r < bound, (op, r)
+    mix = rng.rng_calibrate_valu(3)
+    assert 0 < mix < bound / 15
