@@ -109,9 +109,11 @@ int rng_generate(int g, uint32_t *d_state, uint64_t n_streams, uint64_t n, int t
 /* Same, with an explicit launch shape: wg in {64,128,256,512,1024} lanes per
  * workgroup and unroll in {1,2,4,8,16} samples per generation-loop step.
  * rng_generate uses the autotuned shape when one is loaded, else a default;
- * for XS256 rows of whole multiples of 4 KiB (n % 1024 == 0) it takes at
+ * for XS256 rows of an odd number of 4 KiB (n = 1024 (2i + 1)) it takes at
  * least 512 lanes, which generate each row as four jumped chunks so that
- * concurrent writes spread over four column slots. */
+ * concurrent writes spread over four column slots (for an even number the
+ * chunk starts would share one or two slots, so those rows keep the plain
+ * order at every shape). */
 int rng_generate_ex(int g, uint32_t *d_state, uint64_t n_streams, uint64_t n, int t,
                     void *d_out, uint32_t wg, uint32_t unroll, void *stream);
 

@@ -151,13 +151,20 @@ Shape tuned_shape(int g, int dt)
     return s;
 }
 
+// XS256 rows of an odd number of 4 KiB (N = 1024 (2i + 1)) run as four
+// jumped chunks on 512- and 1024-lane workgroups: chunk c starts c N bytes
+// into its row, so the four chunks of a row cover four column slots of 1 KiB.
+// For an even number the chunk starts share at most two slots (N = 2048) or
+// one (N = 4096 m), and the plain order is faster.
+bool xs256_chunked_rows(uint64_t N) { return N % 1024 == 0 && (N / 1024) % 2 == 1; }
+
 // The shape rng_generate uses for n samples per stream: the tuned one, except
-// that XS256 rows of whole 4 KiB multiples take 512-lane workgroups (their
-// four-chunk path; the tuned shape is measured on other row lengths).
+// that XS256 rows taking the four-chunk path get 512-lane workgroups (the
+// tuned shape is measured on other row lengths).
 Shape row_shape(int g, int dt, uint64_t n)
 {
     Shape s = tuned_shape(g, dt);
-    if (g == RNG_XS256 && n % 1024 == 0 && s.wg < 512) s.wg = 512;
+    if (g == RNG_XS256 && xs256_chunked_rows(n) && s.wg < 512) s.wg = 512;
     return s;
 }
 
@@ -338,7 +345,7 @@ int generate_impl(int g, int dt, uint32_t *d_state, uint64_t ld, uint64_t S, uin
         if (P > 1) return check_launch(generate_few(g, dt, d_state, ld, S, N, c, P, d_out, tab, st), "rng_generate");
     }
     choose_chunks(g, S, N, kGenTile, &a.C, &a.P, kGenLanes);
-    // XS256 rows of whole 4 KiB multiples (no rotated order: a row would need
+    // XS256 rows of an odd number of 4 KiB (no rotated order: a row would need
     // a 256 x 256 jump inside the write stream): four chunks per stream, each
     // jumped once at its start, before any store (one table product per
     // nonzero hexadecimal digit of j N / 4: one for N = 1024), so that the
@@ -346,9 +353,9 @@ int generate_impl(int g, int dt, uint32_t *d_state, uint64_t ld, uint64_t S, uin
     // workgroups of 8+ waves: they hold all four chunks of their groups and
     // write the states back themselves, and their 32-sample tiles measured
     // faster here than 4-wave workgroups with 128-sample tiles (XS256 2^20 x
-    // 1024: 832-867 us at 512 lanes against 1090-1127 at 256 and 887-949 for
+    // 1024: 832-867 us at 512 lanes against 1090-1127 at 256 and 883-949 for
     // the plain order).
-    if (g == RNG_XS256 && staged && a.P == 1 && a.vec4 && S % 64 == 0 && N % 1024 == 0 && shape.wg >= 512) {
+    if (g == RNG_XS256 && staged && a.P == 1 && a.vec4 && S % 64 == 0 && xs256_chunked_rows(N) && shape.wg >= 512) {
         a.C = N / kXs256RowChunks;
         a.P = kXs256RowChunks;
     }

@@ -382,13 +382,30 @@ def test_fold_parity(rng, torch, oracle, name, dt, S, N):
     assert np.array_equal(_host(st), ref_st)
 
 
+@pytest.mark.parametrize("N", [1024, 2048, 3072, 4096, 5120, 8192])
+@pytest.mark.parametrize("dt", ["u32", "f32"])
+def test_xs256_4k_rows_default_shape(rng, torch, oracle, N, dt):
+    """rng_generate on XS256 rows of whole 4 KiB multiples: the odd multiples
+    take 512-lane workgroups and four jumped chunks, the even ones the tuned
+    shape in the plain order; every sample and the written-back states."""
+    g, o, t = rng.RNG_XS256, oracle.XS256, rng.DTYPES[dt]
+    S = 4160
+    st = _dev_state(torch, rng, g, 53, S)
+    out = _gen(torch, rng, g, st, S, N, t)
+    ref_st = oracle.seed(o, 53, S)
+    ref = oracle.generate(o, ref_st, N, t, threads=16)
+    assert np.array_equal(out.view(np.uint32), ref.view(np.uint32))
+    assert np.array_equal(_host(st), ref_st)
+
+
 @pytest.mark.parametrize("N", [1024, 2048, 3072, 4096])
 @pytest.mark.parametrize("S", [64, 192, 4096])
 @pytest.mark.parametrize("wg", [512, 1024])
 @pytest.mark.parametrize("dt", ["u32", "f32"])
 def test_xs256_whole_4k_rows_as_chunks(rng, torch, oracle, N, S, wg, dt):
-    """XS256 rows of whole 4 KiB multiples on 512- and 1024-lane workgroups run
-    as four jumped chunks per row (chunk c starts c N / 4 samples in); two
+    """XS256 rows of an odd number of 4 KiB (1024, 3072) on 512- and 1024-lane
+    workgroups run as four jumped chunks per row (chunk c starts c N / 4
+    samples in), rows of an even number (2048, 4096) in the plain order; two
     calls in a row: every sample and the written-back states of both."""
     g, o, t = rng.RNG_XS256, oracle.XS256, rng.DTYPES[dt]
     st = _dev_state(torch, rng, g, 31, S)
