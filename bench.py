@@ -322,12 +322,13 @@ def small_workloads(torch, R, dev):
     st = torch.empty((2, S), dtype=torch.int32, device=dev)
     R.rng_seed(g, 0, 0, S, st)
     o = torch.empty(S * N, dtype=torch.int32, device=dev)
-    # the launch shape tuned for this size (the bulk size below keeps its own)
-    prev = R.rng_get_shape(g, R.RNG_U32)
+    # the launch shape tuned for this size (rows of 4 KiB: the shape class of
+    # 16 KiB runs, restored afterwards for the other workloads)
+    prev = R.rng_row_shape(g, R.RNG_U32, S, N)
     scratch = torch.empty_like(st)
     R.rng_seed(g, 0, 0, S, scratch)
     wg, un, _ = R.rng_autotune(g, R.RNG_U32, S, N, scratch, o, 5)
-    R.rng_set_shape(g, R.RNG_U32, *prev)
+    R.rng_set_row_shape(g, R.RNG_U32, S, N, *prev)
     ms = _time(torch, lambda: R.rng_generate_ex(g, st, S, N, R.RNG_U32, o, wg, un), 200)
     # the same call 100 times in one captured HIP graph: the device time per
     # call without the host's launch overhead
@@ -385,6 +386,7 @@ def split_workload(torch, R, dev):
                                        "GSamples_s": round(total / (ms * 1e-3) / 1e9, 1),
                                        "GB_s": round(4 * total / (ms * 1e-3) / 1e9, 1),
                                        "samples_per_thread": C,
+                                       "generation_shape": list(R.rng_row_shape(g, R.RNG_U32, rows, C)),
                                        "generation_ms": round(gen_ms, 3),
                                        "generation_GB_s": round(gen_bytes / (gen_ms * 1e-3) / 1e9, 1),
                                        "setup_ms": round(max(ms - gen_ms, 0.0), 3)}

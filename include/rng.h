@@ -109,11 +109,12 @@ int rng_generate(int g, uint32_t *d_state, uint64_t n_streams, uint64_t n, int t
 /* Same, with an explicit launch shape: wg in {64,128,256,512,1024} lanes per
  * workgroup and unroll in {1,2,4,8,16} samples per generation-loop step.
  * rng_generate uses the autotuned shape when one is loaded, else a default;
- * for XS256 rows of an odd number of 4 KiB (n = 1024 (2i + 1)) it takes at
- * least 512 lanes, which generate each row as four jumped chunks so that
- * concurrent writes spread over four column slots (for an even number the
- * chunk starts would share one or two slots, so those rows keep the plain
- * order at every shape). */
+ * rows of 4 or 8 KiB over whole groups of runs have a shape of their own
+ * (below), and for other XS256 rows of an odd number of 4 KiB
+ * (n = 1024 (2i + 1)) it takes at least 512 lanes, which generate each row
+ * as four jumped chunks so that concurrent writes spread over four column
+ * slots (for an even number the chunk starts would share one or two slots,
+ * so those rows keep the plain order at every shape). */
 int rng_generate_ex(int g, uint32_t *d_state, uint64_t n_streams, uint64_t n, int t,
                     void *d_out, uint32_t wg, uint32_t unroll, void *stream);
 
@@ -121,9 +122,21 @@ int rng_generate_ex(int g, uint32_t *d_state, uint64_t n_streams, uint64_t n, in
  * every (wg, unroll) pair on the given problem (d_state_scratch and
  * d_out_scratch are overwritten; reps timed launches per shape).  The paper
  * chose block sizes with an occupancy calculator and unrolled its main loop
- * (Sec. III.A.1, III.B); the choice here is measured. */
+ * (Sec. III.A.1, III.B); the choice here is measured.
+ *
+ * Shapes are kept per row class.  Rows of 4 or 8 KiB (n = 1024 or 2048)
+ * over a stream count that is a multiple of 256 or 128 are written as 16 KiB
+ * runs of 4 or 2 adjacent rows per lane (on workgroups of up to 256 lanes),
+ * and have a shape of their own (default 64 lanes, unroll 16); every other
+ * problem uses the shape that rng_set_shape / rng_get_shape address (default
+ * 256 lanes, unroll 8).  rng_autotune keeps its pick for the class of the
+ * problem it timed; rng_set_row_shape sets, and rng_row_shape reads, the
+ * shape rng_generate will use for n_streams x n (for XS256 rows of an odd
+ * number of 4 KiB outside the run class, at least 512 lanes). */
 int rng_set_shape(int g, int t, uint32_t wg, uint32_t unroll);
 int rng_get_shape(int g, int t, uint32_t *wg, uint32_t *unroll);
+int rng_set_row_shape(int g, int t, uint64_t n_streams, uint64_t n, uint32_t wg, uint32_t unroll);
+int rng_row_shape(int g, int t, uint64_t n_streams, uint64_t n, uint32_t *wg, uint32_t *unroll);
 int rng_autotune(int g, int t, uint64_t n_streams, uint64_t n, uint32_t *d_state_scratch,
                  void *d_out_scratch, uint32_t reps, uint32_t *best_wg, uint32_t *best_unroll,
                  float *best_us, void *stream);

@@ -49,6 +49,8 @@ _SIGS = {
     "rng_generate_ex": (_int, [_int, _vp, _u64, _u64, _int, _vp, _u32, _u32, _vp]),
     "rng_set_shape": (_int, [_int, _int, _u32, _u32]),
     "rng_get_shape": (_int, [_int, _int, _pu32, _pu32]),
+    "rng_set_row_shape": (_int, [_int, _int, _u64, _u64, _u32, _u32]),
+    "rng_row_shape": (_int, [_int, _int, _u64, _u64, _pu32, _pu32]),
     "rng_autotune": (_int, [_int, _int, _u64, _u64, _vp, _vp, _u32, _pu32, _pu32,
                             ctypes.POINTER(ctypes.c_float), _vp]),
     "rng_skip": (_int, [_int, _vp, _u64, _u64, _vp]),
@@ -209,6 +211,16 @@ def rng_set_shape(g, t, wg, unroll):
 def rng_get_shape(g, t):
     wg, un = ctypes.c_uint32(), ctypes.c_uint32()
     _check(_lib.rng_get_shape(g, t, ctypes.byref(wg), ctypes.byref(un)), "rng_get_shape")
+    return wg.value, un.value
+
+
+def rng_set_row_shape(g, t, n_streams, n, wg, unroll):
+    return _check(_lib.rng_set_row_shape(g, t, n_streams, n, wg, unroll), "rng_set_row_shape")
+
+
+def rng_row_shape(g, t, n_streams, n):
+    wg, un = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(_lib.rng_row_shape(g, t, n_streams, n, ctypes.byref(wg), ctypes.byref(un)), "rng_row_shape")
     return wg.value, un.value
 
 

@@ -141,13 +141,26 @@ int gen_words(int g)
 }
 
 static std::mutex g_shape_mu;
-static Shape g_shape[6][2] = {};
+static Shape g_shape[2][6][2] = {};  // [rows written as runs][generator][dtype]
 
-Shape tuned_shape(int g, int dt)
+// Rows of 4 or 8 KiB (n = 1024, 2048) over whole groups of 64 runs are
+// written as 16 KiB runs of 4 or 2 adjacent rows per lane (on workgroups of
+// up to 256 lanes, when the launch is resident): streams per run, else 0.
+uint32_t run_rows(uint64_t S, uint64_t N)
+{
+    if (N != 1024 && N != 2048) return 0;
+    const uint32_t seg = (uint32_t)(4096 / N);
+    return S && S % (64 * (uint64_t)seg) == 0 ? seg : 0;
+}
+
+// Untuned defaults: 256 lanes, unroll 8 (measured on 1 KiB rows), and for
+// runs 64 lanes, unroll 16 (within about 1 % of the fastest shape for every
+// generator at 2^20 x 1024; 256 x 8 ran 15 % slower for XS256 and KISS).
+Shape tuned_shape(int g, int dt, bool runs)
 {
     std::lock_guard<std::mutex> lk(g_shape_mu);
-    Shape s = g_shape[g][dt];
-    if (!s.wg) s = Shape{256, 8};
+    Shape s = g_shape[runs][g][dt];
+    if (!s.wg) s = runs ? Shape{64, 16} : Shape{256, 8};
     return s;
 }
 
@@ -158,20 +171,22 @@ Shape tuned_shape(int g, int dt)
 // one (N = 4096 m), and the plain order is faster.
 bool xs256_chunked_rows(uint64_t N) { return N % 1024 == 0 && (N / 1024) % 2 == 1; }
 
-// The shape rng_generate uses for n samples per stream: the tuned one, except
-// that XS256 rows taking the four-chunk path get 512-lane workgroups (the
-// tuned shape is measured on other row lengths).
-Shape row_shape(int g, int dt, uint64_t n)
+// The shape rng_generate uses for S streams of n samples: the one tuned for
+// runs when the rows are written as runs, else the other one, except that
+// XS256 rows taking the four-chunk path get 512-lane workgroups (the tuned
+// shape is measured on other row lengths).
+Shape row_shape(int g, int dt, uint64_t S, uint64_t n)
 {
-    Shape s = tuned_shape(g, dt);
+    if (run_rows(S, n)) return tuned_shape(g, dt, true);
+    Shape s = tuned_shape(g, dt, false);
     if (g == RNG_XS256 && xs256_chunked_rows(n) && s.wg < 512) s.wg = 512;
     return s;
 }
 
-void set_tuned_shape(int g, int dt, Shape s)
+void set_tuned_shape(int g, int dt, bool runs, Shape s)
 {
     std::lock_guard<std::mutex> lk(g_shape_mu);
-    g_shape[g][dt] = s;
+    g_shape[runs][g][dt] = s;
 }
 
 bool valid_shape(uint32_t wg, uint32_t unroll)
@@ -355,6 +370,10 @@ int generate_impl(int g, int dt, uint32_t *d_state, uint64_t ld, uint64_t S, uin
     // faster here than 4-wave workgroups with 128-sample tiles (XS256 2^20 x
     // 1024: 832-867 us at 512 lanes against 1090-1127 at 256 and 883-949 for
     // the plain order).
+    // rows of 4 or 8 KiB on workgroups of up to 256 lanes: runs of 4 or 2
+    // adjacent rows per lane, 16 KiB each (when the launch is resident; else
+    // the orders below)
+    if (staged && a.P == 1 && a.vec4 && shape.wg <= 256) a.seg = run_rows(S, N);
     if (g == RNG_XS256 && staged && a.P == 1 && a.vec4 && S % 64 == 0 && xs256_chunked_rows(N) && shape.wg >= 512) {
         a.C = N / kXs256RowChunks;
         a.P = kXs256RowChunks;
@@ -418,7 +437,7 @@ int split_run(int g, const uint32_t *d_state_one, uint64_t total, uint64_t n_thr
     }
     const uint64_t rem = total - (T - 1) * C;  // samples of the last thread
     const uint64_t full = rem == C ? T : T - 1;
-    Shape shape = row_shape(g, t, C);
+    Shape shape = row_shape(g, t, full / 64 * 64, C);
     // whole 64-thread groups in one launch (the resident schedule needs them),
     // the rest of the full threads in a second
     const uint64_t full64 = full / 64 * 64;
@@ -544,7 +563,7 @@ int rng_generate(int g, uint32_t *d_state, uint64_t n_streams, uint64_t n, int t
 {
     if (check_gen(g)) return RNG_EINVAL;
     if (t != RNG_U32 && t != RNG_F32) return fail(RNG_EINVAL, "unknown dtype %d", t);
-    Shape s = row_shape(g, t, n);
+    Shape s = row_shape(g, t, n_streams, n);
     return rng_generate_ex(g, d_state, n_streams, n, t, d_out, s.wg, s.unroll, stream);
 }
 

@@ -20,9 +20,10 @@ int check_sizes(uint64_t S, uint64_t N, uint64_t words);
 int device_tables(DevTables *out);
 int gen_words(int g);
 bool valid_shape(uint32_t wg, uint32_t unroll);
-Shape tuned_shape(int g, int dt);
-Shape row_shape(int g, int dt, uint64_t n);
-void set_tuned_shape(int g, int dt, Shape s);
+uint32_t run_rows(uint64_t S, uint64_t N);
+Shape tuned_shape(int g, int dt, bool runs);
+Shape row_shape(int g, int dt, uint64_t S, uint64_t n);
+void set_tuned_shape(int g, int dt, bool runs, Shape s);
 // Chunks per stream: the largest power of two p with S p <= target_lanes and
 // chunks of at least the generator's minimum length.
 void choose_chunks(int g, uint64_t S, uint64_t N, uint64_t align, uint64_t *C, uint32_t *P, uint64_t target_lanes);

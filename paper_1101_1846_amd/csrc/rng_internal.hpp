@@ -61,6 +61,7 @@ struct GenArgs {
     uint32_t nt;      // non-temporal store hint
     uint32_t resident; // waves stride over 64-stream groups with preloaded states (set by the launcher)
     uint32_t rot;      // rows of whole 4 KiB multiples (all but XS256): rotated tile order (constants below)
+    uint32_t seg;      // > 1: rows of 4 or 8 KiB written as runs of seg adjacent rows per lane (if resident)
     DevTables tab;
     uint64_t rot_mwc32[4];     // a^(d N / 4) * 2^64 mod m, d = 0..3
     uint32_t rot_xs32[4][32];  // columns of the xorshift32 M^(d N / 4) (XS32, KISS)

@@ -2,7 +2,8 @@
 // The paper picked block sizes with an occupancy calculator and unrolled its
 // main loop with a pragma (Sec. III.A, III.B); here every (workgroup size,
 // unroll) pair is timed on the device and the fastest is kept per
-// (generator, dtype).
+// (generator, dtype) and row class: rows written as 16 KiB runs (4 or 8 KiB
+// rows) or any other rows.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,7 +21,7 @@ int rng_set_shape(int g, int t, uint32_t wg, uint32_t unroll)
     if (check_gen(g)) return RNG_EINVAL;
     if (t != RNG_U32 && t != RNG_F32) return fail(RNG_EINVAL, "unknown dtype %d", t);
     if (!valid_shape(wg, unroll)) return fail(RNG_EINVAL, "launch shape wg=%u unroll=%u", wg, unroll);
-    set_tuned_shape(g, t, Shape{wg, unroll});
+    set_tuned_shape(g, t, false, Shape{wg, unroll});
     return RNG_OK;
 }
 
@@ -29,7 +30,27 @@ int rng_get_shape(int g, int t, uint32_t *wg, uint32_t *unroll)
     if (check_gen(g)) return RNG_EINVAL;
     if (t != RNG_U32 && t != RNG_F32) return fail(RNG_EINVAL, "unknown dtype %d", t);
     if (!wg || !unroll) return fail(RNG_EINVAL, "NULL output");
-    Shape s = tuned_shape(g, t);
+    Shape s = tuned_shape(g, t, false);
+    *wg = s.wg;
+    *unroll = s.unroll;
+    return RNG_OK;
+}
+
+int rng_set_row_shape(int g, int t, uint64_t n_streams, uint64_t n, uint32_t wg, uint32_t unroll)
+{
+    if (check_gen(g)) return RNG_EINVAL;
+    if (t != RNG_U32 && t != RNG_F32) return fail(RNG_EINVAL, "unknown dtype %d", t);
+    if (!valid_shape(wg, unroll)) return fail(RNG_EINVAL, "launch shape wg=%u unroll=%u", wg, unroll);
+    set_tuned_shape(g, t, run_rows(n_streams, n) != 0, Shape{wg, unroll});
+    return RNG_OK;
+}
+
+int rng_row_shape(int g, int t, uint64_t n_streams, uint64_t n, uint32_t *wg, uint32_t *unroll)
+{
+    if (check_gen(g)) return RNG_EINVAL;
+    if (t != RNG_U32 && t != RNG_F32) return fail(RNG_EINVAL, "unknown dtype %d", t);
+    if (!wg || !unroll) return fail(RNG_EINVAL, "NULL output");
+    Shape s = row_shape(g, t, n_streams, n);
     *wg = s.wg;
     *unroll = s.unroll;
     return RNG_OK;
@@ -87,7 +108,7 @@ int rng_autotune(int g, int t, uint64_t n_streams, uint64_t n, uint32_t *d_state
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
-    set_tuned_shape(g, t, bs);
+    set_tuned_shape(g, t, run_rows(n_streams, n) != 0, bs);
     *best_wg = bs.wg;
     *best_unroll = bs.unroll;
     if (best_us) *best_us = best;

@@ -127,6 +127,39 @@ def test_shape_roundtrip(rng):
     rng.rng_set_shape(g, t, *old)
 
 
+def test_row_shape_classes(rng):
+    """Rows of 4 or 8 KiB over whole groups of runs (a multiple of 256
+    streams at n = 1024, 128 at 2048) keep a shape of their own; every other
+    problem uses rng_set_shape's, and XS256 rows of an odd number of 4 KiB
+    outside the run class take at least 512 lanes."""
+    L = rng.raw()
+    t = rng.RNG_U32
+    for name, g in rng.GENERATORS.items():
+        main = rng.rng_get_shape(g, t)
+        runs = rng.rng_row_shape(g, t, 1 << 20, 1024)
+        assert rng.rng_row_shape(g, t, 1 << 19, 2048) == runs
+        assert rng.rng_row_shape(g, t, 1 << 20, 256) == main
+        assert rng.rng_row_shape(g, t, (1 << 20) + 128, 2048) == runs
+        other = rng.rng_row_shape(g, t, (1 << 20) + 64, 1024)   # not a whole number of runs
+        if g == rng.RNG_XS256:
+            assert other == (max(main[0], 512), main[1])
+            assert rng.rng_row_shape(g, t, 4096, 3072) == (max(main[0], 512), main[1])
+            assert rng.rng_row_shape(g, t, 4096, 4096) == main
+        else:
+            assert other == main
+        rng.rng_set_row_shape(g, t, 256, 1024, 128, 2)
+        assert rng.rng_row_shape(g, t, 1 << 20, 1024) == (128, 2)
+        assert rng.rng_get_shape(g, t) == main
+        rng.rng_set_row_shape(g, t, 256, 1024, *runs)
+        assert rng.rng_row_shape(g, t, 1 << 20, 1024) == runs
+    wg, un = ctypes.c_uint32(), ctypes.c_uint32()
+    assert L.rng_row_shape(99, t, 256, 1024, ctypes.byref(wg), ctypes.byref(un)) == rng.RNG_EINVAL
+    assert L.rng_row_shape(rng.RNG_XS32, 7, 256, 1024, ctypes.byref(wg), ctypes.byref(un)) == rng.RNG_EINVAL
+    assert L.rng_row_shape(rng.RNG_XS32, t, 256, 1024, None, None) == rng.RNG_EINVAL
+    assert L.rng_set_row_shape(rng.RNG_XS32, t, 256, 1024, 100, 8) == rng.RNG_EINVAL
+    assert L.rng_set_row_shape(rng.RNG_XS32, t, 256, 1024, 256, 3) == rng.RNG_EINVAL
+
+
 def test_split_validation(rng):
     L = rng.raw()
     for name, g in rng.GENERATORS.items():

@@ -152,6 +152,26 @@ def test_autotune_keeps_values(rng, torch, oracle):
     rng.rng_set_shape(g, rng.RNG_U32, *old)
 
 
+def test_autotune_runs_class(rng, torch, oracle):
+    """Tuning on rows of 4 KiB (written as runs) keeps its pick for that class
+    only; rng_generate then uses it, bit-exact."""
+    g, S, N, t = rng.RNG_XS256, 1 << 14, 1024, rng.RNG_U32
+    st = torch.empty((8, S), dtype=torch.int32, device="cuda")
+    out = torch.empty(S * N, dtype=torch.int32, device="cuda")
+    main, runs0 = rng.rng_get_shape(g, t), rng.rng_row_shape(g, t, S, N)
+    rng.rng_seed(g, 3, 0, S, st)
+    wg, un, us = rng.rng_autotune(g, t, S, N, st, out, 2)
+    assert us > 0 and rng.rng_row_shape(g, t, S, N) == (wg, un)
+    assert rng.rng_get_shape(g, t) == main
+    rng.rng_seed(g, 5, 0, S, st)
+    rng.rng_generate(g, st, S, N, t, out)
+    ref_st = oracle.seed(oracle.XS256, 5, S)
+    ref = oracle.generate(oracle.XS256, ref_st, N, threads=THREADS)
+    assert np.array_equal(_u32(out).reshape(S, N), ref)
+    assert np.array_equal(_u32(st), ref_st)
+    rng.rng_set_row_shape(g, t, S, N, *runs0)
+
+
 def _check_requests(oracle, tab, names, where, offs, idx, host_out, base_word, host_pools, seed):
     """Every sample and the final state of requests idx against the oracle:
     the output from one serial pass from the stream's seeded state, the final

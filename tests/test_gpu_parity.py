@@ -321,12 +321,38 @@ def test_rotated_rows_parity(rng, torch, oracle, name, dt, S, N, shape):
     assert np.array_equal(_host(st), ref_st)
 
 
+# Rows of 4 and 8 KiB on up to 256 lanes, stream counts a multiple of 256 or
+# 128: each lane writes the rows of 4 or 2 adjacent streams as one 16 KiB run
+# (other counts take the orders above).
+SEG_ROWS = [(16384, 1024, (256, 8)), (16640, 1024, (128, 16)), (8192, 2048, (64, 4)), (256, 1024, (256, 1)),
+            (131584, 2048, (256, 2)), (2304, 1024, (64, 16))]
+
+
 @pytest.mark.parametrize("name", GENS)
-def test_rotated_rows_full_queue(rng, torch, oracle, name):
-    """2^20 streams x 1024 with a full register queue per wave, twice in a row
-    (the written-back states must continue the rows)."""
+@pytest.mark.parametrize("dt", ["u32", "f32"])
+@pytest.mark.parametrize("S,N,shape", SEG_ROWS)
+def test_segmented_rows_parity(rng, torch, oracle, name, dt, S, N, shape):
+    """Two calls in a row: every sample and the written-back states."""
     g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
-    S, N = 1 << 20, 1024
+    t = rng.DTYPES[dt]
+    st = _dev_state(torch, rng, g, 17, S)
+    ref_st = oracle.seed(o, 17, S)
+    for _ in range(2):
+        out = _gen(torch, rng, g, st, S, N, t, shape=shape)
+        ref = oracle.generate(o, ref_st, N, t, threads=16)
+        assert np.array_equal(out.view(np.uint32), ref.view(np.uint32))
+        assert np.array_equal(_host(st), ref_st)
+        del out, ref
+
+
+@pytest.mark.parametrize("name", GENS)
+@pytest.mark.parametrize("S", [1 << 20, (1 << 20) - 64])
+def test_rotated_rows_full_queue(rng, torch, oracle, name, S):
+    """2^20 streams x 1024 with a full register queue per wave (runs of four
+    rows), and 2^20 - 64 (the rotated order, or for XS256 the plain one),
+    twice in a row: the written-back states must continue the rows."""
+    g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
+    N = 1024
     st = _dev_state(torch, rng, g, 16, S)
     ref_st = oracle.seed(o, 16, S)
     for _ in range(2):
