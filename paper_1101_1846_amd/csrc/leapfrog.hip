@@ -145,12 +145,16 @@ __global__ __launch_bounds__(256) void k_leapfrog(LeapArgs a)
     __shared__ uint4 s_t4[kTable ? 2048 : 1];
     __shared__ uint32_t s_t8[kBytes ? 1024 : 1];
     if constexpr (kTable) {
-        stage_t4(s_t4, (const uint4 *)((const char *)a.dconst + kConstBytes + kColBytes));
+        stage_quads<256, 2048>(s_t4, (const uint4 *)((const char *)a.dconst + kConstBytes + kColBytes));
         __syncthreads();
     }
     if constexpr (kBytes) {
         const uint32_t *t8 = (const uint32_t *)((const char *)a.dconst + kConstBytes);
-        for (uint32_t i = threadIdx.x; i < 1024; i += 256) s_t8[i] = t8[i];
+        uint32_t v[4];  // every load in flight before the LDS writes
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = t8[i * 256 + threadIdx.x];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s_t8[i * 256 + threadIdx.x] = v[i];
         __syncthreads();
     }
     const uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x;

@@ -50,8 +50,7 @@ __global__ __launch_bounds__(kTreeWG) void k_tree_level(uint32_t *__restrict__ w
         const uint32_t b0 = (uint32_t)__builtin_ctzll(unit) + shift;
         const bool staged = (unit & (unit - 1)) == 0 && b0 <= 60;
         if (staged) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) stage_t4(s_t4[k], tab.xs256_t4 + (size_t)(b0 + k) * 2048);
+            stage_quads<kTreeWG, 4 * 2048>(&s_t4[0][0], tab.xs256_t4 + (size_t)b0 * 2048);  // tables b0 .. b0+3
             __syncthreads();
         }
         for (uint64_t i = first; i < n; i += stride) {

@@ -95,8 +95,8 @@ __global__ __launch_bounds__(kLevelWG) void k_batch_level(BatchArgs a, uint32_t 
     // pow is 0xFFFFFFFF when C is no power of two: compare without adding to it
     const bool staged = h.has_xs256 && L.pow <= 64 - kRadixBits;
     if (staged) {
-#pragma unroll
-        for (int k = 0; k < kRadixBits; ++k) stage_t4(s_t4[k], a.tab.xs256_t4 + (size_t)(L.pow + k) * 2048);
+        // tables L.pow .. L.pow + kRadixBits - 1, adjacent in memory
+        stage_quads<kLevelWG, kRadixBits * 2048>(&s_t4[0][0], a.tab.xs256_t4 + (size_t)L.pow * 2048);
     }
     const uint32_t lo = 1u << L.shift;
     for (uint32_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {

@@ -140,11 +140,21 @@ __device__ __forceinline__ void gf2_apply256_t4(const uint4 *T, uint32_t (&x)[8]
     for (int i = 0; i < 8; ++i) x[i] = r[i];
 }
 
-// Copies one 32 KiB lookup table into LDS with the whole workgroup (the
-// caller synchronises before use).
-__device__ __forceinline__ void stage_t4(uint4 *lds, const uint4 *T)
+// Copies NQ consecutive 16-byte quads (whole lookup tables of 2048 quads,
+// 32 KiB) into LDS with a workgroup of WG lanes, every global load issued
+// before the first LDS write: one memory round trip, where a loop strided by
+// the runtime workgroup size waits for each quad in turn.  The caller
+// synchronises before use.
+template <int WG, int NQ>
+__device__ __forceinline__ void stage_quads(uint4 *lds, const uint4 *T)
 {
-    for (uint32_t i = threadIdx.x; i < 2048; i += blockDim.x) lds[i] = T[i];
+    static_assert(NQ % WG == 0, "whole rows of the workgroup");
+    constexpr int PER = NQ / WG;
+    uint4 v[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) v[i] = T[i * WG + threadIdx.x];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) lds[i * WG + threadIdx.x] = v[i];
 }
 
 // ---------------------------------------------------------------- generators
