@@ -15,7 +15,7 @@
 #include "rng_batch_internal.hpp"
 
 namespace rngx {
-int launch_batch_root(const BatchArgs &a, uint32_t max_requests, hipStream_t s);
+int launch_batch_root(const BatchArgs &a, const PlanInline &pin, uint32_t max_requests, hipStream_t s);
 int launch_batch_level(const BatchArgs &a, uint32_t level, unsigned grid, hipStream_t s);
 int launch_batch_gen(const BatchArgs &a, int wg, int unroll, unsigned grid, hipStream_t s);
 int batch_gen_occupancy(int wg, int unroll, int *blocks_per_cu);
@@ -432,11 +432,19 @@ int rng_batch_launch(rng_batch_t *h, void *stream)
     hipStream_t st = (hipStream_t)stream;
     const BatchHeader &H = h->hdr();
     hipError_t e;
-    // the whole plan in one copy
-    if ((e = hipMemcpyAsync(h->d_plan, h->h_plan, H.plan_bytes, hipMemcpyHostToDevice, st)) != hipSuccess)
-        return hip_fail(e, "rng_batch_launch: upload");
-    if ((e = hipEventRecord(h->copied, st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    h->copy_pending = true;
+    // a small plan in the root kernel's arguments (direct launches), else the
+    // whole plan in one copy
+    static thread_local PlanInline pin;
+    pin.bytes = 0;
+    if (!h->use_graph && H.plan_bytes <= kInlinePlanBytes) {
+        pin.bytes = H.plan_bytes;
+        std::memcpy(pin.q, h->h_plan, H.plan_bytes);
+    } else {
+        if ((e = hipMemcpyAsync(h->d_plan, h->h_plan, H.plan_bytes, hipMemcpyHostToDevice, st)) != hipSuccess)
+            return hip_fail(e, "rng_batch_launch: upload");
+        if ((e = hipEventRecord(h->copied, st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        h->copy_pending = true;
+    }
 
     if (h->occ_wg != h->wg || h->occ_unroll != h->unroll) {
         int per_cu = 0;
@@ -451,7 +459,7 @@ int rng_batch_launch(rng_batch_t *h, void *stream)
     if (!h->use_graph) {
         // root (and tree level 0), the further tree levels, persistent generation
         const BatchArgs a = make_args(h, tab);
-        int rc = launch_batch_root(a, h->max_requests, st);
+        int rc = launch_batch_root(a, pin, h->max_requests, st);
         for (uint32_t l = 1; !rc && l < H.levels; ++l) rc = launch_batch_level(a, l, level_grid, st);
         if (!rc) rc = launch_batch_gen(a, (int)h->wg, (int)h->unroll, gen_grid, st);
         return check_launch(rc, "rng_batch_launch");
@@ -467,7 +475,8 @@ int rng_batch_launch(rng_batch_t *h, void *stream)
         hipStream_t cs = h->capture;
         if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return hip_fail(e, "hipStreamBeginCapture");
-        int rc = launch_batch_root(a, h->max_requests, cs);
+        pin.bytes = 0;  // the graph's root kernel reads the uploaded plan
+        int rc = launch_batch_root(a, pin, h->max_requests, cs);
         // level 0 (chunks 1..15 of every request) is done by the root kernel
         for (uint32_t l = 1; !rc && l < H.levels; ++l) rc = launch_batch_level(a, l, level_grid, cs);
         if (!rc) rc = launch_batch_gen(a, (int)h->wg, (int)h->unroll, gen_grid, cs);

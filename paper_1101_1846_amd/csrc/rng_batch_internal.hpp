@@ -80,6 +80,19 @@ struct BatchHeader {
     BatchGroup groups[kBatchMaxGroups];
 };
 
+// Plans of at most kInlinePlanBytes travel in the root kernel's arguments
+// instead of an upload (direct launches only: a captured graph keeps the
+// arguments it was recorded with).  The root kernel reads the plan there, and
+// its first workgroup writes it to the device plan buffer for the kernels
+// that follow it on the stream.  This saves the copy and the wait for it.
+constexpr uint32_t kInlinePlanBytes = 2048;
+
+struct PlanInline {
+    uint32_t bytes;  // 0: the plan was uploaded to BatchArgs::hdr
+    uint32_t pad[3];
+    uint4 q[kInlinePlanBytes / 16];
+};
+
 struct BatchArgs {
     const BatchHeader *hdr;       // the packed plan
     uint32_t *chunk_req;          // [64 * n_tiles] sorted request index of every chunk (padded group order)

@@ -33,11 +33,14 @@ __device__ __forceinline__ void with_gen(uint32_t g, F &&f)
 // kernel's tile counter.
 constexpr int kRootWG = 256;
 
-__global__ __launch_bounds__(kRootWG) void k_batch_root(BatchArgs a)
+__global__ __launch_bounds__(kRootWG) void k_batch_root(BatchArgs a, PlanInline pin)
 {
     __shared__ uint32_t s_st[8 * kRootWG];  // leader states, [word][lane]
-    const BatchHeader &h = *a.hdr;
-    const BatchReq *reqs = plan_at<const BatchReq>(a.hdr, h.off_reqs);
+    const BatchHeader *hp = pin.bytes ? (const BatchHeader *)pin.q : a.hdr;
+    if (pin.bytes && blockIdx.x == 0)  // the plan for the kernels after this one
+        for (uint32_t i = threadIdx.x; i * 16 < pin.bytes; i += kRootWG) ((uint4 *)a.hdr)[i] = pin.q[i];
+    const BatchHeader &h = *hp;
+    const BatchReq *reqs = plan_at<const BatchReq>(hp, h.off_reqs);
     if (blockIdx.x == 0 && threadIdx.x == 0) a.counter[0] = 0;  // tile counter of the generation kernel
     const uint32_t j = threadIdx.x & 15, lead = threadIdx.x & ~15u;
     // uniform over the workgroup: every lane takes part in each barrier
@@ -146,11 +149,11 @@ __global__ __launch_bounds__(kLevelWG) void k_batch_level(BatchArgs a, uint32_t 
 }
 
 // ------------------------------------------------------------------ launchers
-int launch_batch_root(const BatchArgs &a, uint32_t max_requests, hipStream_t s)
+int launch_batch_root(const BatchArgs &a, const PlanInline &pin, uint32_t max_requests, hipStream_t s)
 {
     const uint64_t lanes = (uint64_t)max_requests * 16, blocks = (lanes + kRootWG - 1) / kRootWG;
     const unsigned grid = (unsigned)(blocks < 1024 ? blocks : 1024);
-    hipLaunchKernelGGL(k_batch_root, dim3(grid ? grid : 1), dim3(kRootWG), 0, s, a);
+    hipLaunchKernelGGL(k_batch_root, dim3(grid ? grid : 1), dim3(kRootWG), 0, s, a, pin);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

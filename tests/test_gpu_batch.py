@@ -239,6 +239,34 @@ def test_batch_plans_of_different_sizes(rng, torch, oracle, use_graph):
         rng.rng_batch_destroy(h)
 
 
+def test_batch_small_plans_back_to_back(rng, torch, oracle):
+    """Small plans travel in the root kernel's arguments, and the root kernel
+    writes them to the device plan buffer for the kernels after it: four
+    one- and two-request plans launched back to back on one stream with no
+    synchronisation in between, then every output checked."""
+    m = Mix(rng, torch, oracle, 12, seed=37, max_len=40000, offsets=False)
+    h = rng.rng_batch_create(16, 1 << 20)
+    try:
+        rng.rng_batch_set_shape(h, 0, 0, 64)
+        subsets = ([3], [5, 8], [11], [0, 3])
+        runs = {i: 0 for i in range(12)}
+        for subset in subsets:
+            rng.rng_batch_set(h, m.requests(subset))
+            rng.rng_batch_launch(h)
+            for i in subset:
+                runs[i] += 1
+        torch.cuda.synchronize()
+        got = _u32(m.out)
+        pools = {g: _u32(p) for g, p in m.pool.items()}
+        for i in {i for sub in subsets for i in sub}:
+            exp, st = m.expected(i, runs[i])
+            n = int(m.length[i])
+            assert np.array_equal(got[m.offs[i]:m.offs[i] + n], exp), i
+            assert np.array_equal(pools[m.gen[i]][:, m.idx[i]], st), (i, "state")
+    finally:
+        rng.rng_batch_destroy(h)
+
+
 def test_batch_validation(rng, torch):
     h = rng.rng_batch_create(4, 1000)
     st = torch.empty(8, dtype=torch.int32, device="cuda")
