@@ -135,7 +135,9 @@ def step_table(db, bench_line):
     names (launch_shapes), averaged over the timed launches only: the last
     `steps` dispatches of each before the run's first torch fill kernel (the
     write-ceiling measurement that follows the timed steps).  Beside each, the
-    same run's HIP-event average from the JSON line."""
+    same run's HIP-event average from the JSON line (per_kernel: an untimed
+    pass with an event at every launch boundary; for the dominant kernel also
+    the timed steps' own events, roofline.avg_launch_ms)."""
     line = json.load(open(bench_line))
     steps = line["steps"]
     rows = [(short(n, 10 ** 6), st, dur) for n, st, dur in _rows(db, "select name, start, duration from kernels "
@@ -144,13 +146,16 @@ def step_table(db, bench_line):
     t_fill = fills[0] if fills else float("inf")
     out = ["| kernel | timed launches | trace avg us | trace min us | trace max us | bench event avg us |",
            "|---|---|---|---|---|---|"]
+    dom = line["roofline"]["kernel"]
     for key, sh in line["launch_shapes"].items():
         g, d = key.split("_")
         pat = "k_generate<Gen%s, %d, %d, %d, 128, 2>" % (g, 1 if d == "f32" else 0, sh["wg"], sh["unroll"])
         durs = [dur / 1000.0 for n, st, dur in rows if pat in n and st < t_fill][-steps:]
-        ev = line["per_kernel"][key]["ms"] * 1e3
-        out.append("| %s | %d | %.2f | %.2f | %.2f | %.2f |" % (pat, len(durs), sum(durs) / len(durs), min(durs),
-                                                              max(durs), ev))
+        ev = "%.2f" % (line["per_kernel"][key]["ms"] * 1e3)
+        if "<%s>" % key in dom:
+            ev += " (timed steps: %.2f)" % (line["roofline"]["avg_launch_ms"] * 1e3)
+        out.append("| %s | %d | %.2f | %.2f | %.2f | %s |" % (pat, len(durs), sum(durs) / len(durs), min(durs),
+                                                            max(durs), ev))
     return "\n".join(out)
 
 
