@@ -17,6 +17,7 @@
 namespace rngx {
 int launch_batch_root(const BatchArgs &a, const PlanInline &pin, uint32_t max_requests, hipStream_t s);
 int launch_batch_level(const BatchArgs &a, uint32_t level, unsigned grid, hipStream_t s);
+int launch_batch_tree_small(const BatchArgs &a, const PlanInline &pin, uint32_t n, hipStream_t s);
 int launch_batch_gen(const BatchArgs &a, int wg, int unroll, unsigned grid, hipStream_t s);
 int batch_gen_occupancy(int wg, int unroll, int *blocks_per_cu);
 }  // namespace rngx
@@ -382,7 +383,9 @@ static int plan(rng_batch_t *h, const rng_request_t *reqs, uint32_t n)
     const bool pow2 = (C & (C - 1)) == 0;
     const uint32_t lc = (uint32_t)__builtin_ctzll(C);
     uint32_t S = 0, B = 0;
-    for (uint32_t l = 1; l < levels; ++l) {  // level 0 is done by the root kernel
+    H.lvl[0] = LevelInfo{};  // level 0 is done by the root kernel: only its table power (small-batch tree)
+    H.lvl[0].pow = pow2 && lc + kRadixBits <= 64 ? lc : 0xFFFFFFFFu;
+    for (uint32_t l = 1; l < levels; ++l) {
         LevelInfo &L = H.lvl[l];
         L.seg_off = S;
         L.shift = kRadixBits * l;
@@ -459,8 +462,14 @@ int rng_batch_launch(rng_batch_t *h, void *stream)
     if (!h->use_graph) {
         // root (and tree level 0), the further tree levels, persistent generation
         const BatchArgs a = make_args(h, tab);
-        int rc = launch_batch_root(a, pin, h->max_requests, st);
-        for (uint32_t l = 1; !rc && l < H.levels; ++l) rc = launch_batch_level(a, l, level_grid, st);
+        int rc;
+        if (pin.bytes && H.levels <= kSmallTreeLevels && H.n <= kSmallTreeRequests) {
+            // the whole tree of each request in one workgroup: one launch instead of 1 + levels - 1
+            rc = launch_batch_tree_small(a, pin, H.n, st);
+        } else {
+            rc = launch_batch_root(a, pin, h->max_requests, st);
+            for (uint32_t l = 1; !rc && l < H.levels; ++l) rc = launch_batch_level(a, l, level_grid, st);
+        }
         if (!rc) rc = launch_batch_gen(a, (int)h->wg, (int)h->unroll, gen_grid, st);
         return check_launch(rc, "rng_batch_launch");
     }

@@ -87,6 +87,12 @@ struct BatchHeader {
 // that follow it on the stream.  This saves the copy and the wait for it.
 constexpr uint32_t kInlinePlanBytes = 2048;
 
+// Small plans whose requests need at most kSmallTreeLevels radix-16 levels
+// (16^3 chunks) and that hold at most kSmallTreeRequests requests build every
+// request's tree in one workgroup of one launch (k_batch_tree_small).
+constexpr uint32_t kSmallTreeLevels = 3;
+constexpr uint32_t kSmallTreeRequests = 64;
+
 struct PlanInline {
     uint32_t bytes;  // 0: the plan was uploaded to BatchArgs::hdr
     uint32_t pad[3];

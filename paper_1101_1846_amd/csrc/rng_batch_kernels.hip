@@ -148,12 +148,84 @@ __global__ __launch_bounds__(kLevelWG) void k_batch_level(BatchArgs a, uint32_t 
     }
 }
 
+// Small batches (the plan in the kernel's arguments, at most 16^3 chunks per
+// request): the whole radix-16 tree of each request in one workgroup, one
+// request per workgroup, with the levels separated by barriers instead of
+// launches.  Lane 0 jumps the request's state by `offset` (as the root
+// kernel's leader); level l then starts chunks [16^l, 16^(l+1)) from chunk
+// j mod 16^l, jumped by (j - j mod 16^l) C, XS256 with the four tables of
+// M^(C 16^l 2^k), k < 4, staged in LDS when C is a power of two.
+constexpr int kTreeSmallWG = 1024;
+
+__global__ __launch_bounds__(kTreeSmallWG) void k_batch_tree_small(BatchArgs a, PlanInline pin)
+{
+    __shared__ uint4 s_t4[kRadixBits * 2048];
+    const BatchHeader &h = *(const BatchHeader *)pin.q;
+    if (blockIdx.x == 0) {  // the plan for the generation kernel, and its tile counter
+        for (uint32_t i = threadIdx.x; i * 16 < pin.bytes; i += kTreeSmallWG) ((uint4 *)a.hdr)[i] = pin.q[i];
+        if (threadIdx.x == 0) a.counter[0] = 0;
+    }
+    const uint32_t r = blockIdx.x;
+    if (r >= h.n) return;  // uniform per workgroup
+    const BatchReq q = plan_at<const BatchReq>(&h, h.off_reqs)[r];
+    const BatchGroup &gr = h.groups[q.group];
+    uint32_t *ws = a.ws + gr.ws_off;
+    uint32_t *map = a.chunk_req + gr.tile_begin * 64 + q.chunk_base;
+    if (threadIdx.x == 0) {
+        if (q.nchunks) map[0] = r;
+        with_gen(gr.gen, [&]<class G>() {
+            G g;
+            g.load(q.state, q.stride, 0, a.tab);
+            if (q.offset) g.jump(q.offset, a.tab);
+            if (q.nchunks == 0) g.store(q.state, q.stride, 0);
+            else g.store(ws, gr.nchunks_pad, q.chunk_base);
+        });
+    }
+    const bool xs = gr.gen == (uint32_t)G_XS256;
+    for (uint32_t l = 0, lo = 1; lo < q.nchunks; ++l, lo <<= kRadixBits) {
+        const uint32_t pw = h.lvl[0].pow == 0xFFFFFFFFu ? 0xFFFFFFFFu : h.lvl[0].pow + kRadixBits * l;
+        const bool staged = xs && pw <= 64 - kRadixBits;  // uniform per workgroup
+        __syncthreads();  // the previous level's states are written, and its tables read
+        if (staged) {
+            stage_quads<kTreeSmallWG, kRadixBits * 2048>(s_t4, a.tab.xs256_t4 + (size_t)pw * 2048);
+            __syncthreads();
+        }
+        const uint32_t hi = min(lo << kRadixBits, q.nchunks);
+        for (uint32_t j = lo + threadIdx.x; j < hi; j += kTreeSmallWG) {
+            const uint32_t rem = j & (lo - 1), qd = j >> (kRadixBits * l);  // qd in 1 .. 15
+            map[j] = r;
+            with_gen(gr.gen, [&]<class G>() {
+                G g;
+                g.load(ws, gr.nchunks_pad, q.chunk_base + rem, a.tab);
+                if constexpr (G::kId == G_XS256) {
+                    if (staged) {
+#pragma unroll
+                        for (int b = 0; b < kRadixBits; ++b)
+                            if ((qd >> b) & 1) g.jump_table(s_t4 + b * 2048);
+                    } else {
+                        g.jump((uint64_t)(j - rem) * h.C, a.tab);
+                    }
+                } else {
+                    g.jump((uint64_t)(j - rem) * h.C, a.tab);
+                }
+                g.store(ws, gr.nchunks_pad, q.chunk_base + j);
+            });
+        }
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 int launch_batch_root(const BatchArgs &a, const PlanInline &pin, uint32_t max_requests, hipStream_t s)
 {
     const uint64_t lanes = (uint64_t)max_requests * 16, blocks = (lanes + kRootWG - 1) / kRootWG;
     const unsigned grid = (unsigned)(blocks < 1024 ? blocks : 1024);
     hipLaunchKernelGGL(k_batch_root, dim3(grid ? grid : 1), dim3(kRootWG), 0, s, a, pin);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_batch_tree_small(const BatchArgs &a, const PlanInline &pin, uint32_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_tree_small, dim3(n ? n : 1), dim3(kTreeSmallWG), 0, s, a, pin);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

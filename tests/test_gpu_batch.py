@@ -267,6 +267,51 @@ def test_batch_small_plans_back_to_back(rng, torch, oracle):
         rng.rng_batch_destroy(h)
 
 
+@pytest.mark.parametrize("chunk", [64, 192])
+@pytest.mark.parametrize("name", GENS)
+def test_batch_small_tree(rng, torch, oracle, chunk, name):
+    """Small plans (at most 16^3 chunks per request, in the kernel's
+    arguments) build every request's radix-16 tree in one workgroup: one
+    request per batch with 1, 15, 16, 17, 255, 256, 257 and 4096 chunks, then
+    all eight in one batch, some with an offset; 64-sample chunks (XS256 from
+    LDS-staged tables) and 192 (no power of two: the global digit tables).
+    Every sample and every final state against the oracle."""
+    g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
+    counts = [1, 15, 16, 17, 255, 256, 257, 4096]
+    lengths = [c * chunk - (chunk // 2 if c > 1 else 0) for c in counts]
+    offsets = [0, 0, 12345, 0, 0, 999, 0, (1 << 33) + 7]
+    n = len(counts)
+    W = rng.rng_state_words(g)
+    st = torch.empty((W, n), dtype=torch.int32, device="cuda")
+    rng.rng_seed(g, 71, 0, n, st)
+    offs, pos = [], 0
+    for L in lengths:
+        offs.append(pos)
+        pos += (L + 31) // 32 * 32
+    out = torch.zeros(pos, dtype=torch.int32, device="cuda")
+    ref_st = oracle.seed(o, 71, n)
+    h = rng.rng_batch_create(16, 1 << 22)
+    try:
+        rng.rng_batch_set_shape(h, 0, 0, chunk)
+        for subset in [[i] for i in range(n)] + [list(range(n))]:
+            reqs = [(g, 0, st.data_ptr() + 4 * i, n, offsets[i], lengths[i], out.data_ptr() + 4 * offs[i])
+                    for i in subset]
+            rng.rng_batch_set(h, reqs)
+            rng.rng_batch_launch(h)
+            torch.cuda.synchronize()
+            got = _u32(out)
+            for i in subset:
+                one = ref_st[:, i:i + 1].copy()
+                if offsets[i]:
+                    oracle.skip(o, one, offsets[i])
+                exp = oracle.generate(o, one, lengths[i])[0].view(np.uint32)
+                ref_st[:, i] = one[:, 0]
+                assert np.array_equal(got[offs[i]:offs[i] + lengths[i]], exp), (subset, i)
+            assert np.array_equal(_u32(st), ref_st), subset
+    finally:
+        rng.rng_batch_destroy(h)
+
+
 def test_batch_validation(rng, torch):
     h = rng.rng_batch_create(4, 1000)
     st = torch.empty(8, dtype=torch.int32, device="cuda")
