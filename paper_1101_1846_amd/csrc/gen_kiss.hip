@@ -3,4 +3,5 @@
 
 namespace rngx {
 RNGX_INSTANTIATE(GenKISS)
+RNGX_INSTANTIATE_TREE_HEAD(GenKISS)
 }  // namespace rngx

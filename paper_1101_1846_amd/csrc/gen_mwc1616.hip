@@ -3,4 +3,5 @@
 
 namespace rngx {
 RNGX_INSTANTIATE(GenMWC1616)
+RNGX_INSTANTIATE_TREE_HEAD(GenMWC1616)
 }  // namespace rngx

@@ -3,4 +3,5 @@
 
 namespace rngx {
 RNGX_INSTANTIATE(GenMWC32)
+RNGX_INSTANTIATE_TREE_HEAD(GenMWC32)
 }  // namespace rngx

@@ -3,4 +3,5 @@
 
 namespace rngx {
 RNGX_INSTANTIATE(GenXS256)
+RNGX_INSTANTIATE_TREE_HEAD(GenXS256)
 }  // namespace rngx

@@ -3,4 +3,5 @@
 
 namespace rngx {
 RNGX_INSTANTIATE(GenXS32)
+RNGX_INSTANTIATE_TREE_HEAD(GenXS32)
 }  // namespace rngx

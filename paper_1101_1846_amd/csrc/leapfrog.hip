@@ -241,9 +241,10 @@ int rng_generate_leapfrog(int g, const uint32_t *d_state_one, uint64_t total, ui
     if (int rc = device_tables(&tab)) return rc;
     uint32_t *ws = (uint32_t *)d_workspace;
     uint32_t *dconst = (uint32_t *)((char *)d_workspace + align256(T * gen_words(g) * 4));
-    // thread j starts at state_j: state_0 copied to slot 0, then a radix-16 tree
-    int rc = check_launch(dispatch_state_copy(g, d_state_one, 1, 0, ws, T, 0, st), "leapfrog: init");
-    for (uint32_t shift = 0; !rc && ((uint64_t)1 << shift) < T; shift += 4)
+    // thread j starts at state_j: a radix-16 tree, its first three levels (with
+    // the copy of state_0) in one launch
+    int rc = check_launch(dispatch_tree_head(g, d_state_one, ws, T, 1, tab, st), "leapfrog: tree head");
+    for (uint32_t shift = kTreeHeadShift; !rc && ((uint64_t)1 << shift) < T; shift += 4)
         rc = check_launch(dispatch_tree_level(g, ws, T, shift, 1, tab, st), "leapfrog: tree level");
     if (rc) return rc;
     if (g == RNG_MWC1616 || g == RNG_KISS) {

@@ -272,6 +272,12 @@ int dispatch_seed(int g, uint64_t seed, uint64_t first, uint64_t S, uint32_t *st
     RNGX_GEN_SWITCH(g, launch_seed_t<G>(seed, first, S, st, tab, s))
 }
 
+int dispatch_tree_head(int g, const uint32_t *st0, uint32_t *ws, uint64_t T, uint64_t unit, const DevTables &tab,
+                       hipStream_t s)
+{
+    RNGX_GEN_SWITCH(g, launch_tree_head_t<G>(st0, ws, T, unit, tab, s))
+}
+
 int dispatch_tree_level(int g, uint32_t *ws, uint64_t T, uint32_t shift, uint64_t unit, const DevTables &tab,
                         hipStream_t s)
 {
@@ -426,12 +432,13 @@ int split_run(int g, const uint32_t *d_state_one, uint64_t total, uint64_t n_thr
     if (int rc = split_scratch_bytes(g, total, n_threads, &need)) return rc;
     if (ws_bytes < need)
         return fail(RNG_ENOMEM, "workspace %llu bytes < %llu", (unsigned long long)ws_bytes, (unsigned long long)need);
-    int rc = check_launch(dispatch_state_copy(g, d_state_one, 1, 0, ws, T, 0, st), "split: init");
-    if (rc) return rc;
-    // radix-16 tree: level l starts threads [16^l, 16^(l+1)) from threads below 16^l
+    // radix-16 tree: level l starts threads [16^l, 16^(l+1)) from threads below 16^l;
+    // the start state's copy and levels 0 .. 2 in one launch
     uint64_t far;
     if (mul_overflows(C, T, &far)) return fail(RNG_ERANGE, "jump distance overflows");
-    for (uint32_t shift = 0; ((uint64_t)1 << shift) < T; shift += 4) {
+    int rc = check_launch(dispatch_tree_head(g, d_state_one, ws, T, C, tab, st), "split: tree head");
+    if (rc) return rc;
+    for (uint32_t shift = kTreeHeadShift; ((uint64_t)1 << shift) < T; shift += 4) {
         rc = check_launch(dispatch_tree_level(g, ws, T, shift, C, tab, st), "split: tree level");
         if (rc) return rc;
     }

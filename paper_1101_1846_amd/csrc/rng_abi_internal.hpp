@@ -37,6 +37,14 @@ int dispatch_skip(int g, uint32_t *st, uint64_t ld, uint64_t S, uint64_t k, cons
 // of ws ([W][T]) from the threads below 2^shift, unit samples per thread index.
 int dispatch_tree_level(int g, uint32_t *ws, uint64_t T, uint32_t shift, uint64_t unit, const DevTables &tab,
                         hipStream_t s);
+// Thread starts 0 .. min(T, 4096) - 1 of a split or leapfrogged sequence
+// from one state (k_tree_head); the further tree levels start at shift 12.
+template <class G>
+int launch_tree_head_t(const uint32_t *st0, uint32_t *ws, uint64_t T, uint64_t unit, const DevTables &tab,
+                       hipStream_t stream);
+int dispatch_tree_head(int g, const uint32_t *st0, uint32_t *ws, uint64_t T, uint64_t unit, const DevTables &tab,
+                       hipStream_t s);
+constexpr uint32_t kTreeHeadShift = 12;
 int dispatch_state_copy(int g, const uint32_t *src, uint64_t ss, uint64_t si, uint32_t *dst, uint64_t ds,
                         uint64_t di, hipStream_t s);
 

@@ -204,7 +204,8 @@ def test_skip_many_states(rng, torch, oracle, name, k):
 @pytest.mark.parametrize("total,threads", [(1, 1), (1000, 1), (1000, 7), (4096 * 7 + 3, 64), (100000, 1000),
                                           (65536, 65536), (5, 8), (1024 * 192 + 900, 193),
                                           (1024 * 384, 384), (2048 * 64, 64), (1024, 1),
-                                          (1024 * 512 + 600, 513), (2048 * 128 + 2000, 129)])
+                                          (1024 * 512 + 600, 513), (2048 * 128 + 2000, 129),
+                                          ((1 << 22) + 5, (1 << 21) + 3)])
 def test_split_parity(rng, torch, oracle, name, total, threads):
     """Sequence splitting (Sec. II.A.4): the concatenated thread outputs equal the
     serial sequence of the one logical stream, and the final state matches.
@@ -213,7 +214,9 @@ def test_split_parity(rng, torch, oracle, name, total, threads):
     rows in a first launch, 64 in a second) and a 900-sample tail; 1024 * 384
     over 384 and 2048 * 64 over 64: whole 4 KiB rows only.  1024 * 512 + 600
     over 513 and 2048 * 128 + 2000 over 129: 512 (128) full rows written as
-    16 KiB runs from thread states at a stride of 513 (129), then the tail."""
+    16 KiB runs from thread states at a stride of 513 (129), then the tail.
+    2^22 + 5 over 2^21 + 3: two samples per thread, a sixth tree level whose
+    2^20 XS256 chains stride over a capped grid."""
     g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
     st1 = _dev_state(torch, rng, g, 2, 1)
     ws_bytes = rng.rng_split_workspace_bytes(g, threads)
@@ -230,7 +233,7 @@ def test_split_parity(rng, torch, oracle, name, total, threads):
 @pytest.mark.parametrize("name", GENS)
 @pytest.mark.parametrize("dt", ["u32", "f32"])
 @pytest.mark.parametrize("total,threads", [(1, 1), (1000, 1), (1000, 7), (4096 * 7 + 3, 64), (100000, 1000),
-                                          (65536, 65536), (5, 8), (77777, 4096)])
+                                          (65536, 65536), (5, 8), (77777, 4096), (3 << 21, (1 << 21) + 5)])
 def test_leapfrog_parity(rng, torch, oracle, name, dt, total, threads):
     """Leapfrogging (Sec. II.A.4): thread j's numbers j, j + T, ... interleave into
     the serial sequence of the one logical stream; the final state matches."""
