@@ -27,7 +27,20 @@ namespace rngx {
 
 namespace {
 
-constexpr int kSkipWG = 256;  // XS256: one column of M^k per thread
+constexpr int kSkipWG = 256;
+// XS256 workgroups take 1024 lanes: the first 256 carry one column of M^k
+// each while the table is built, then all of them apply it (16 waves per CU
+// share the LDS reads; with four, each wave's products ran one after the
+// other and the launch took 0.10 ms for 2^20 states).  Splitting each
+// column's products over the four lanes of a quad (nibbles 4m + s on lane s,
+// partial sums combined by DPP) made it slower, 84 against 70 us: the four
+// lanes read four table rows at once, whose entries share LDS banks.
+constexpr int kSkipXs256WG = 1024;
+template <class G>
+constexpr int skip_wg()
+{
+    return G::kId == G_XS256 ? kSkipXs256WG : kSkipWG;
+}
 constexpr uint64_t kXs256TableMin = (uint64_t)1 << 16;
 
 struct SkipArgs {
@@ -56,8 +69,9 @@ __device__ __forceinline__ uint32_t lds_t392_index(const uint16_t *t, uint32_t a
 }
 
 template <class G>
-__global__ __launch_bounds__(kSkipWG) void k_skip_by(SkipArgs a)
+__global__ __launch_bounds__(skip_wg<G>()) void k_skip_by(SkipArgs a)
 {
+    constexpr int WG = skip_wg<G>();
     constexpr bool kMwc16 = G::kId == G_MWC1616 || G::kId == G_KISS;
     constexpr bool kXs32 = G::kId == G_XS32 || G::kId == G_KISS;
     constexpr bool kXs256 = G::kId == G_XS256;
@@ -68,7 +82,7 @@ __global__ __launch_bounds__(kSkipWG) void k_skip_by(SkipArgs a)
     __shared__ uint32_t s_col[kXs256 ? 256 * 8 : 1];       // columns of M^k
     const uint32_t tid = threadIdx.x;
     if constexpr (kMwc16) {
-        for (uint32_t i = tid; i < (uint32_t)kMwc16Count; i += kSkipWG) {
+        for (uint32_t i = tid; i < (uint32_t)kMwc16Count; i += WG) {
             const uint32_t ai = a.tab.t392[i];
             const uint32_t *p = a.tab.mwc16_pow + (size_t)i * 64;
             uint32_t c = (uint32_t)(((uint64_t)1 << 48) % (ai * 65536u - 1u));  // fold image of 1
@@ -80,7 +94,7 @@ __global__ __launch_bounds__(kSkipWG) void k_skip_by(SkipArgs a)
     }
     if constexpr (kXs32) {
         // entry p * 256 + v: XOR of columns 8p + j over the set bits j of v
-        for (uint32_t e = tid; e < 1024; e += kSkipWG) {
+        for (uint32_t e = tid; e < 1024; e += WG) {
             const uint32_t p = e >> 8, v = e & 255;
             uint32_t r = 0;
             for (int j = 0; j < 8; ++j)
@@ -89,6 +103,7 @@ __global__ __launch_bounds__(kSkipWG) void k_skip_by(SkipArgs a)
         }
     }
     if constexpr (kXs256) {
+        const bool colt = tid < 256;  // thread c < 256 carries column c
         uint32_t col[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) col[i] = (uint32_t)(tid / 32 == (uint32_t)i) << (tid % 32);
@@ -97,7 +112,7 @@ __global__ __launch_bounds__(kSkipWG) void k_skip_by(SkipArgs a)
         // into registers while the current one is applied; buffer b & 1 is
         // rewritten only after the barrier that follows the previous write,
         // which every thread reaches after applying what that buffer held.
-        constexpr int Q = 2048 / kSkipWG;
+        constexpr int Q = 2048 / WG;
         uint32_t rest = 0;  // non-zero: the host returns before launching for k = 0
         for (int j = 0; j < 16; ++j)
             if ((a.k >> (4 * j)) & 15) rest |= 1u << j;
@@ -107,26 +122,27 @@ __global__ __launch_bounds__(kSkipWG) void k_skip_by(SkipArgs a)
         uint4 pre[Q];
         const uint4 *src = table(__builtin_ctz(rest));
 #pragma unroll
-        for (int i = 0; i < Q; ++i) pre[i] = src[tid + i * kSkipWG];
+        for (int i = 0; i < Q; ++i) pre[i] = src[tid + i * WG];
         for (uint32_t buf = 0;; buf ^= 1) {
             uint4 *t = s_t4 + buf * 2048;
 #pragma unroll
-            for (int i = 0; i < Q; ++i) t[tid + i * kSkipWG] = pre[i];
+            for (int i = 0; i < Q; ++i) t[tid + i * WG] = pre[i];
             __syncthreads();
             rest &= rest - 1;
             if (rest) {
                 src = table(__builtin_ctz(rest));
 #pragma unroll
-                for (int i = 0; i < Q; ++i) pre[i] = src[tid + i * kSkipWG];
+                for (int i = 0; i < Q; ++i) pre[i] = src[tid + i * WG];
             }
-            gf2_apply256_t4(t, col);
+            if (colt) gf2_apply256_t4(t, col);
             if (!rest) break;
         }
+        if (colt)
 #pragma unroll
-        for (int i = 0; i < 8; ++i) s_col[tid * 8 + i] = col[i];
+            for (int i = 0; i < 8; ++i) s_col[tid * 8 + i] = col[i];
         __syncthreads();
         // quad q = (2p + h) * 16 + v: words 4h .. 4h+3 of the XOR of columns 4p + j over the set bits j of v
-        for (uint32_t q = tid; q < 2048; q += kSkipWG) {
+        for (uint32_t q = tid; q < 2048; q += WG) {
             const uint32_t p = q >> 5, h = (q >> 4) & 1, v = q & 15;
             uint32_t r[4] = {0, 0, 0, 0};
             for (int j = 0; j < 4; ++j)
@@ -136,8 +152,8 @@ __global__ __launch_bounds__(kSkipWG) void k_skip_by(SkipArgs a)
         }
     }
     if constexpr (kMwc16 || kXs32 || kXs256) __syncthreads();
-    const uint64_t stride = (uint64_t)gridDim.x * kSkipWG;
-    for (uint64_t s = (uint64_t)blockIdx.x * kSkipWG + tid; s < a.S; s += stride) {
+    const uint64_t stride = (uint64_t)gridDim.x * WG;
+    for (uint64_t s = (uint64_t)blockIdx.x * WG + tid; s < a.S; s += stride) {
         G g;
         g.load(a.st, a.ld, s, a.tab);
         if constexpr (G::kId == G_MWC32) {
@@ -183,10 +199,11 @@ int launch_skip_by(const SkipArgs &a, hipStream_t stream)
     // workgroups that build LDS tables stride over the states: one per CU
     // for XS256 (one staged table per nonzero hexadecimal digit of k), two
     // for MWC16
+    constexpr int WG = skip_wg<G>();
     const uint64_t cap = G::kId == G_XS256 ? 256 : (G::kId == G_MWC1616 || G::kId == G_KISS) ? 512 : 4096;
-    const uint64_t need = (a.S + kSkipWG - 1) / kSkipWG;
+    const uint64_t need = (a.S + WG - 1) / WG;
     const unsigned blocks = (unsigned)(need < cap ? need : cap);
-    hipLaunchKernelGGL(k_skip_by<G>, dim3(blocks), dim3(kSkipWG), 0, stream, a);
+    hipLaunchKernelGGL(k_skip_by<G>, dim3(blocks), dim3(WG), 0, stream, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
