@@ -154,8 +154,38 @@ __global__ __launch_bounds__(kLevelWG) void k_batch_level(BatchArgs a, uint32_t 
 // launches.  Lane 0 jumps the request's state by `offset` (as the root
 // kernel's leader); level l then starts chunks [16^l, 16^(l+1)) from chunk
 // j mod 16^l, jumped by (j - j mod 16^l) C, XS256 with the four tables of
-// M^(C 16^l 2^k), k < 4, staged in LDS when C is a power of two.
+// M^(C 16^l 2^k), k < 4, staged in LDS when C is a power of two (level 2 by
+// tree_small_stride4).
 constexpr int kTreeSmallWG = 1024;
+
+// XS256 level 2 of such a tree (chunks [256, hi) from chunks r < 256), four
+// lanes per r: lane k starts chunk r + 256 (k + 1) with the staged tables of
+// M^(256 C 2^b) for the set bits b of k + 1, then each chunk 4 * 256 further
+// on with one product by M^(1024 C), at most 5 products in a row where the
+// bit tables take up to 4 for each of two chunks per lane.  t4 holds the
+// tables of M^(256 C 2^b), b < 4.
+__device__ __forceinline__ void tree_small_stride4(uint32_t *ws, uint32_t ld, uint32_t base, uint32_t *map,
+                                                   uint32_t req, uint32_t hi, const uint4 *t4, const DevTables &tab)
+{
+    static_assert(kTreeSmallWG == 1024, "four lanes for each of 256 chunks");
+    const uint32_t k = (threadIdx.x >> 6) & 3, r = (threadIdx.x >> 8) * 64 + (threadIdx.x & 63);
+    if (r + 256 >= hi) return;  // no chunk starts from r
+    const uint32_t room = (hi - 1 - r) >> 8;  // largest q with r + 256 q < hi
+    GenXS256 g;
+    g.load(ws, ld, base + r, tab);
+    for (uint32_t qd = k + 1; qd <= room; qd += 4) {
+        if (qd == k + 1) {
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                if ((qd >> b) & 1) g.jump_table(t4 + b * 2048);
+        } else {
+            g.jump_table(t4 + 2 * 2048);
+        }
+        const uint32_t j = r + (qd << 8);
+        map[j] = req;
+        g.store(ws, ld, base + j);
+    }
+}
 
 __global__ __launch_bounds__(kTreeSmallWG) void k_batch_tree_small(BatchArgs a, PlanInline pin)
 {
@@ -191,6 +221,10 @@ __global__ __launch_bounds__(kTreeSmallWG) void k_batch_tree_small(BatchArgs a, 
             __syncthreads();
         }
         const uint32_t hi = min(lo << kRadixBits, q.nchunks);
+        if (staged && l == 2) {  // uniform: see below
+            tree_small_stride4(ws, gr.nchunks_pad, q.chunk_base, map, r, hi, s_t4, a.tab);
+            continue;
+        }
         for (uint32_t j = lo + threadIdx.x; j < hi; j += kTreeSmallWG) {
             const uint32_t rem = j & (lo - 1), qd = j >> (kRadixBits * l);  // qd in 1 .. 15
             map[j] = r;

@@ -272,14 +272,15 @@ def test_batch_small_plans_back_to_back(rng, torch, oracle):
 def test_batch_small_tree(rng, torch, oracle, chunk, name):
     """Small plans (at most 16^3 chunks per request, in the kernel's
     arguments) build every request's radix-16 tree in one workgroup: one
-    request per batch with 1, 15, 16, 17, 255, 256, 257 and 4096 chunks, then
-    all eight in one batch, some with an offset; 64-sample chunks (XS256 from
-    LDS-staged tables) and 192 (no power of two: the global digit tables).
-    Every sample and every final state against the oracle."""
+    request per batch with 1, 15, 16, 17, 255, 256, 257, 1000, 2049 and 4096
+    chunks, then all ten in one batch, some with an offset; 64-sample chunks
+    (XS256 from LDS-staged tables, level 2 four lanes per source chunk) and
+    192 (no power of two: the global digit tables).  Every sample and every
+    final state against the oracle."""
     g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
-    counts = [1, 15, 16, 17, 255, 256, 257, 4096]
+    counts = [1, 15, 16, 17, 255, 256, 257, 1000, 2049, 4096]
     lengths = [c * chunk - (chunk // 2 if c > 1 else 0) for c in counts]
-    offsets = [0, 0, 12345, 0, 0, 999, 0, (1 << 33) + 7]
+    offsets = [0, 0, 12345, 0, 0, 999, 0, 5, 0, (1 << 33) + 7]
     n = len(counts)
     W = rng.rng_state_words(g)
     st = torch.empty((W, n), dtype=torch.int32, device="cuda")
