@@ -647,7 +647,9 @@ def served_workload(R, single_rate):
             st = R.rng_server_stats(h)
             out["lambda_%d" % lam] = {
                 "requests": n, "p50_us": round(st["p50_us"], 1), "p99_us": round(st["p99_us"], 1),
-                "mean_us": round(st["mean_us"], 1), "offered_GB_s": round(4 * tab["length"].sum() / t[-1] / 1e9, 1),
+                "mean_us": round(st["mean_us"], 1), "mean_queue_submit_device_us":
+                    [round(st["mean_queue_us"], 1), round(st["mean_submit_us"], 1), round(st["mean_device_us"], 1)],
+                "offered_GB_s": round(4 * tab["length"].sum() / t[-1] / 1e9, 1),
                 "GSamples_s": round(st["gsamples_per_s"], 1), "batches": st["batches"],
                 "mean_batch_requests": round(st["mean_batch_requests"], 1)}
         n = 20000

@@ -372,6 +372,10 @@ typedef struct {
     double wall_s;                           /* first arrival -> last completion */
     double gsamples_per_s;
     double mean_batch_requests;
+    /* mean_us in three parts: arrival -> admission into a batch (queue),
+     * admission -> its launches enqueued (host: plan and launch calls),
+     * enqueued -> completion seen by the worker (device, and the poll) */
+    double mean_queue_us, mean_submit_us, mean_device_us;
 } rng_server_stats_t;
 
 typedef struct rng_server rng_server_t;

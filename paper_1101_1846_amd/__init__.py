@@ -100,7 +100,8 @@ class rng_server_stats_t(ctypes.Structure):
                 ("samples", ctypes.c_uint64), ("admission_waits", ctypes.c_uint64), ("p50_us", ctypes.c_double),
                 ("p99_us", ctypes.c_double), ("mean_us", ctypes.c_double), ("max_us", ctypes.c_double),
                 ("wall_s", ctypes.c_double), ("gsamples_per_s", ctypes.c_double),
-                ("mean_batch_requests", ctypes.c_double)]
+                ("mean_batch_requests", ctypes.c_double), ("mean_queue_us", ctypes.c_double),
+                ("mean_submit_us", ctypes.c_double), ("mean_device_us", ctypes.c_double)]
 
 
 _pdbl = ctypes.POINTER(ctypes.c_double)

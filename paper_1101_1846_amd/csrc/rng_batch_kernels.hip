@@ -149,102 +149,122 @@ __global__ __launch_bounds__(kLevelWG) void k_batch_level(BatchArgs a, uint32_t 
 }
 
 // Small batches (the plan in the kernel's arguments, at most 16^3 chunks per
-// request): the whole radix-16 tree of each request in one workgroup, one
-// request per workgroup, with the levels separated by barriers instead of
-// launches.  Lane 0 jumps the request's state by `offset` (as the root
-// kernel's leader); level l then starts chunks [16^l, 16^(l+1)) from chunk
-// j mod 16^l, jumped by (j - j mod 16^l) C, XS256 with the four tables of
-// M^(C 16^l 2^k), k < 4, staged in LDS when C is a power of two (level 2 by
-// tree_small_stride4).
-constexpr int kTreeSmallWG = 1024;
-
-// XS256 level 2 of such a tree (chunks [256, hi) from chunks r < 256), four
-// lanes per r: lane k starts chunk r + 256 (k + 1) with the staged tables of
-// M^(256 C 2^b) for the set bits b of k + 1, then each chunk 4 * 256 further
-// on with one product by M^(1024 C), at most 5 products in a row where the
-// bit tables take up to 4 for each of two chunks per lane.  t4 holds the
-// tables of M^(256 C 2^b), b < 4.
-__device__ __forceinline__ void tree_small_stride4(uint32_t *ws, uint32_t ld, uint32_t base, uint32_t *map,
-                                                   uint32_t req, uint32_t hi, const uint4 *t4, const DevTables &tab)
-{
-    static_assert(kTreeSmallWG == 1024, "four lanes for each of 256 chunks");
-    const uint32_t k = (threadIdx.x >> 6) & 3, r = (threadIdx.x >> 8) * 64 + (threadIdx.x & 63);
-    if (r + 256 >= hi) return;  // no chunk starts from r
-    const uint32_t room = (hi - 1 - r) >> 8;  // largest q with r + 256 q < hi
-    GenXS256 g;
-    g.load(ws, ld, base + r, tab);
-    for (uint32_t qd = k + 1; qd <= room; qd += 4) {
-        if (qd == k + 1) {
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
-                if ((qd >> b) & 1) g.jump_table(t4 + b * 2048);
-        } else {
-            g.jump_table(t4 + 2 * 2048);
-        }
-        const uint32_t j = r + (qd << 8);
-        map[j] = req;
-        g.store(ws, ld, base + j);
-    }
-}
+// request): the whole radix-16 tree of each request in one launch, with the
+// levels separated by barriers instead of launches.  Each request takes four
+// workgroups that need nothing from each other: every one jumps the
+// request's state by `offset` (as the root kernel's leader) and builds
+// chunks 0 .. 255 (levels 0 and 1: chunk j of level l starts from chunk
+// j mod 16^l, jumped by (j - j mod 16^l) C) in its own LDS, workgroup 0
+// writes them out, and the four share level 2 (chunks 256 .. 4095), so its
+// jumps spread over four CUs.  XS256 stages the tables of M^(C 16^l 2^k),
+// k < 4, in LDS when C is a power of two; its level 2 then runs four lanes
+// per source chunk: lane k starts chunk r + 256 (k + 1) with the tables of
+// the set bits of k + 1, then each chunk 1024 further on with one product by
+// M^(1024 C), at most 5 products in a row (the bit tables: up to 4 for each
+// of up to 4 chunks per lane, on one CU, before).
+constexpr int kTreeSmallWG = 256;
+constexpr uint32_t kTreeSmallBlocks = 4;  // workgroups per request
 
 __global__ __launch_bounds__(kTreeSmallWG) void k_batch_tree_small(BatchArgs a, PlanInline pin)
 {
     __shared__ uint4 s_t4[kRadixBits * 2048];
+    __shared__ uint32_t s_st[8 * 256];  // chunks 0 .. 255, [word][chunk]
     const BatchHeader &h = *(const BatchHeader *)pin.q;
     if (blockIdx.x == 0) {  // the plan for the generation kernel, and its tile counter
         for (uint32_t i = threadIdx.x; i * 16 < pin.bytes; i += kTreeSmallWG) ((uint4 *)a.hdr)[i] = pin.q[i];
         if (threadIdx.x == 0) a.counter[0] = 0;
     }
-    const uint32_t r = blockIdx.x;
+    const uint32_t r = blockIdx.x / kTreeSmallBlocks, b = blockIdx.x % kTreeSmallBlocks;
     if (r >= h.n) return;  // uniform per workgroup
     const BatchReq q = plan_at<const BatchReq>(&h, h.off_reqs)[r];
+    if (b > 0 && q.nchunks <= 256) return;  // no level 2: workgroup 0 does it all
     const BatchGroup &gr = h.groups[q.group];
     uint32_t *ws = a.ws + gr.ws_off;
     uint32_t *map = a.chunk_req + gr.tile_begin * 64 + q.chunk_base;
-    if (threadIdx.x == 0) {
-        if (q.nchunks) map[0] = r;
+    const uint32_t ld = gr.nchunks_pad, tid = threadIdx.x;
+    if (tid == 0) {
         with_gen(gr.gen, [&]<class G>() {
             G g;
             g.load(q.state, q.stride, 0, a.tab);
             if (q.offset) g.jump(q.offset, a.tab);
-            if (q.nchunks == 0) g.store(q.state, q.stride, 0);
-            else g.store(ws, gr.nchunks_pad, q.chunk_base);
+            if (b == 0) {
+                if (q.nchunks == 0) g.store(q.state, q.stride, 0);
+                else g.store(ws, ld, q.chunk_base);
+            }
+            g.store(s_st, 256, 0);
         });
+        if (b == 0 && q.nchunks) map[0] = r;
     }
     const bool xs = gr.gen == (uint32_t)G_XS256;
-    for (uint32_t l = 0, lo = 1; lo < q.nchunks; ++l, lo <<= kRadixBits) {
-        const uint32_t pw = h.lvl[0].pow == 0xFFFFFFFFu ? 0xFFFFFFFFu : h.lvl[0].pow + kRadixBits * l;
+    const uint32_t pow0 = h.lvl[0].pow;  // log2 C, or 0xFFFFFFFF
+    // levels 0 and 1: chunks [1, 16) and [16, 256) into LDS
+    for (uint32_t l = 0, lo = 1; l < 2 && lo < q.nchunks; ++l, lo <<= kRadixBits) {
+        const uint32_t pw = pow0 == 0xFFFFFFFFu ? 0xFFFFFFFFu : pow0 + kRadixBits * l;
         const bool staged = xs && pw <= 64 - kRadixBits;  // uniform per workgroup
-        __syncthreads();  // the previous level's states are written, and its tables read
+        __syncthreads();  // the previous level's states are in LDS, and its tables read
         if (staged) {
             stage_quads<kTreeSmallWG, kRadixBits * 2048>(s_t4, a.tab.xs256_t4 + (size_t)pw * 2048);
             __syncthreads();
         }
-        const uint32_t hi = min(lo << kRadixBits, q.nchunks);
-        if (staged && l == 2) {  // uniform: see below
-            tree_small_stride4(ws, gr.nchunks_pad, q.chunk_base, map, r, hi, s_t4, a.tab);
-            continue;
-        }
-        for (uint32_t j = lo + threadIdx.x; j < hi; j += kTreeSmallWG) {
+        const uint32_t hi = min(lo << kRadixBits, q.nchunks), j = lo + tid;
+        if (j < hi) {
             const uint32_t rem = j & (lo - 1), qd = j >> (kRadixBits * l);  // qd in 1 .. 15
-            map[j] = r;
             with_gen(gr.gen, [&]<class G>() {
                 G g;
-                g.load(ws, gr.nchunks_pad, q.chunk_base + rem, a.tab);
+                g.load(s_st, 256, rem, a.tab);
                 if constexpr (G::kId == G_XS256) {
                     if (staged) {
 #pragma unroll
-                        for (int b = 0; b < kRadixBits; ++b)
-                            if ((qd >> b) & 1) g.jump_table(s_t4 + b * 2048);
+                        for (int k = 0; k < kRadixBits; ++k)
+                            if ((qd >> k) & 1) g.jump_table(s_t4 + k * 2048);
                     } else {
                         g.jump((uint64_t)(j - rem) * h.C, a.tab);
                     }
                 } else {
                     g.jump((uint64_t)(j - rem) * h.C, a.tab);
                 }
-                g.store(ws, gr.nchunks_pad, q.chunk_base + j);
+                g.store(s_st, 256, j);
+                if (b == 0) g.store(ws, ld, q.chunk_base + j);
             });
+            if (b == 0) map[j] = r;
         }
+    }
+    // level 2: chunks [256, hi) from the 256 in LDS
+    if (q.nchunks <= 256) return;  // uniform
+    const uint32_t hi = min(256u << kRadixBits, q.nchunks);
+    const uint32_t pw = pow0 == 0xFFFFFFFFu ? 0xFFFFFFFFu : pow0 + 2 * kRadixBits;
+    __syncthreads();
+    if (xs && pw <= 64 - kRadixBits) {
+        stage_quads<kTreeSmallWG, 3 * 2048>(s_t4, a.tab.xs256_t4 + (size_t)pw * 2048);  // M^(256 C 2^k), k < 3
+        __syncthreads();
+        const uint32_t k = tid >> 6, src = b * 64 + (tid & 63);  // four lanes per source chunk
+        if (src + 256 >= hi) return;
+        const uint32_t room = (hi - 1 - src) >> 8;  // largest qd with src + 256 qd < hi
+        GenXS256 g;
+        g.load(s_st, 256, src, a.tab);
+        for (uint32_t qd = k + 1; qd <= room; qd += 4) {
+            if (qd == k + 1) {
+#pragma unroll
+                for (int e = 0; e < 3; ++e)
+                    if ((qd >> e) & 1) g.jump_table(s_t4 + e * 2048);
+            } else {
+                g.jump_table(s_t4 + 2 * 2048);
+            }
+            const uint32_t j = src + (qd << 8);
+            map[j] = r;
+            g.store(ws, ld, q.chunk_base + j);
+        }
+        return;
+    }
+    for (uint32_t j = 256 + b * kTreeSmallWG + tid; j < hi; j += kTreeSmallBlocks * kTreeSmallWG) {
+        const uint32_t rem = j & 255;
+        map[j] = r;
+        with_gen(gr.gen, [&]<class G>() {
+            G g;
+            g.load(s_st, 256, rem, a.tab);
+            g.jump((uint64_t)(j - rem) * h.C, a.tab);
+            g.store(ws, ld, q.chunk_base + j);
+        });
     }
 }
 
@@ -259,7 +279,7 @@ int launch_batch_root(const BatchArgs &a, const PlanInline &pin, uint32_t max_re
 
 int launch_batch_tree_small(const BatchArgs &a, const PlanInline &pin, uint32_t n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_batch_tree_small, dim3(n ? n : 1), dim3(kTreeSmallWG), 0, s, a, pin);
+    hipLaunchKernelGGL(k_batch_tree_small, dim3(n ? n * kTreeSmallBlocks : 1), dim3(kTreeSmallWG), 0, s, a, pin);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

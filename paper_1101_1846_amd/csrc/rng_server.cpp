@@ -82,7 +82,7 @@ class PoolAlloc {
 struct Req {
     uint64_t stream = 0, length = 0, off = 0;
     int dtype = 0;
-    Clock::time_point t_arrive, t_done;
+    Clock::time_point t_arrive, t_admit, t_launched, t_done;
     bool admitted = false, done = false, released = false;
 };
 
@@ -120,6 +120,7 @@ struct rng_server {
     Clock::time_point first_arrival, last_done;
     bool any_arrival = false;
     std::vector<double> lat_us;
+    double queue_us = 0, submit_us = 0, device_us = 0;  // sums over completed requests
 };
 
 static void worker_loop(rng_server *h)
@@ -143,6 +144,9 @@ static void worker_loop(rng_server *h)
                 r.t_done = t;
                 h->busy.erase(r.stream);
                 h->lat_us.push_back(std::chrono::duration<double, std::micro>(t - r.t_arrive).count());
+                h->queue_us += std::chrono::duration<double, std::micro>(r.t_admit - r.t_arrive).count();
+                h->submit_us += std::chrono::duration<double, std::micro>(r.t_launched - r.t_admit).count();
+                h->device_us += std::chrono::duration<double, std::micro>(t - r.t_launched).count();
                 h->samples_done += r.length;
                 ++h->completed;
                 if (h->cfg.auto_release && !r.released) {
@@ -171,6 +175,7 @@ static void worker_loop(rng_server *h)
                 std::unique_lock<std::mutex> lk(h->mu);
                 if (h->stop && h->pending.empty()) break;
                 uint64_t samples = 0;
+                const auto t_admit = Clock::now();
                 for (auto it = h->pending.begin(); it != h->pending.end();) {
                     if (chosen.size() >= h->cfg.max_batch_requests) break;
                     Req &r = h->reqs[*it];
@@ -186,6 +191,7 @@ static void worker_loop(rng_server *h)
                     }
                     r.off = off;
                     r.admitted = true;
+                    r.t_admit = t_admit;
                     samples += r.length;
                     in_batch.insert(r.stream);
                     chosen.push_back(*it);
@@ -217,6 +223,11 @@ static void worker_loop(rng_server *h)
                     h->stop = true;
                     h->cv_done.notify_all();
                     break;
+                }
+                const auto t_launched = Clock::now();
+                {
+                    std::lock_guard<std::mutex> lk(h->mu);
+                    for (uint64_t tk : chosen) h->reqs[tk].t_launched = t_launched;
                 }
                 free_slot->tickets = chosen;
                 free_slot->busy = true;
@@ -408,6 +419,9 @@ int rng_server_stats(rng_server_t *h, rng_server_stats_t *st)
         double s = 0;
         for (double x : v) s += x;
         st->mean_us = s / v.size();
+        st->mean_queue_us = h->queue_us / v.size();
+        st->mean_submit_us = h->submit_us / v.size();
+        st->mean_device_us = h->device_us / v.size();
     }
     if (h->any_arrival && h->completed)
         st->wall_s = std::chrono::duration<double>(h->last_done - h->first_arrival).count();
@@ -420,6 +434,7 @@ int rng_server_reset_stats(rng_server_t *h)
     if (!h) return fail(RNG_EINVAL, "NULL handle");
     std::lock_guard<std::mutex> lk(h->mu);
     h->lat_us.clear();
+    h->queue_us = h->submit_us = h->device_us = 0;
     h->batches = h->batch_requests = h->admission_waits = 0;
     h->samples_done = 0;
     h->any_arrival = false;

@@ -67,6 +67,9 @@ def test_server_results_are_ordered_stream_slices(rng, hip, oracle, idle_spin_us
         st = rng.rng_server_stats(h)
         assert st["completed"] == n and st["batches"] >= 1
         assert 0 < st["p50_us"] <= st["p99_us"] <= st["max_us"]
+        parts = st["mean_queue_us"] + st["mean_submit_us"] + st["mean_device_us"]
+        assert min(st["mean_queue_us"], st["mean_submit_us"], st["mean_device_us"]) >= 0
+        assert abs(parts - st["mean_us"]) <= 1e-6 * st["mean_us"] + 1e-3
         seq, fin = _expected_per_stream(oracle, n_streams, seed, streams, lengths)
         pos = {s: 0 for s in range(n_streams)}
         for i, tk in enumerate(tickets):
