@@ -230,6 +230,51 @@ def test_split_parity(rng, torch, oracle, name, total, threads):
     assert np.array_equal(_host(fin), ref_st[:, 0])
 
 
+# Thread counts at the edges of the start tree's levels (16^2 and 16^3: the
+# one-launch head and the level kernels; 4 * 16^3 - 1: a level whose source
+# threads are not all used), with power-of-two and odd samples per thread.
+TREE_EDGE_T = [255, 256, 257, 4095, 4096, 4097, 16383, 65535, 65537]
+
+
+@pytest.mark.parametrize("name", GENS)
+@pytest.mark.parametrize("T", TREE_EDGE_T)
+@pytest.mark.parametrize("C", [4, 3])
+def test_split_tree_edges(rng, torch, oracle, name, T, C):
+    """Sequence splitting (Sec. II.A.4) with T threads of C samples each (the
+    last one ragged): the concatenated output equals the serial sequence."""
+    g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
+    total = T * C - (C - 1)
+    st1 = _dev_state(torch, rng, g, 5, 1)
+    ws_bytes = rng.rng_split_workspace_bytes(g, T)
+    ws = torch.empty(ws_bytes // 4 + 64, dtype=torch.int32, device="cuda")
+    out = torch.empty(total, dtype=torch.int32, device="cuda")
+    fin = torch.empty(rng.rng_state_words(g), dtype=torch.int32, device="cuda")
+    rng.rng_generate_split(g, st1, total, T, rng.RNG_U32, out, fin, ws, ws_bytes)
+    ref_st = oracle.seed(o, 5, 1)
+    ref = oracle.generate(o, ref_st, total)[0]
+    assert np.array_equal(_host(out), ref), (name, T, C)
+    assert np.array_equal(_host(fin), ref_st[:, 0])
+
+
+@pytest.mark.parametrize("name", GENS)
+@pytest.mark.parametrize("T", TREE_EDGE_T)
+def test_leapfrog_tree_edges(rng, torch, oracle, name, T):
+    """Leapfrogging (Sec. II.A.4) over T threads (unit jumps: the tree's
+    power-of-two path), 3T + 5 numbers."""
+    g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
+    total = 3 * T + 5
+    st1 = _dev_state(torch, rng, g, 6, 1)
+    ws_bytes = rng.rng_leapfrog_workspace_bytes(g, T)
+    ws = torch.empty(ws_bytes // 4 + 64, dtype=torch.int32, device="cuda")
+    out = torch.empty(total, dtype=torch.int32, device="cuda")
+    fin = torch.empty(rng.rng_state_words(g), dtype=torch.int32, device="cuda")
+    rng.rng_generate_leapfrog(g, st1, total, T, rng.RNG_U32, out, fin, ws, ws_bytes)
+    ref_st = oracle.seed(o, 6, 1)
+    ref = oracle.generate(o, ref_st, total)[0]
+    assert np.array_equal(_host(out), ref), (name, T)
+    assert np.array_equal(_host(fin), ref_st[:, 0])
+
+
 @pytest.mark.parametrize("name", GENS)
 @pytest.mark.parametrize("dt", ["u32", "f32"])
 @pytest.mark.parametrize("total,threads", [(1, 1), (1000, 1), (1000, 7), (4096 * 7 + 3, 64), (100000, 1000),
