@@ -464,7 +464,7 @@ int rng_batch_launch(rng_batch_t *h, void *stream)
         const BatchArgs a = make_args(h, tab);
         int rc;
         if (pin.bytes && H.levels <= kSmallTreeLevels && H.n <= kSmallTreeRequests) {
-            // the whole tree of each request in one workgroup: one launch instead of 1 + levels - 1
+            // the whole tree of each request in one launch instead of 1 + levels - 1
             rc = launch_batch_tree_small(a, pin, H.n, st);
         } else {
             rc = launch_batch_root(a, pin, h->max_requests, st);

@@ -89,7 +89,8 @@ constexpr uint32_t kInlinePlanBytes = 2048;
 
 // Small plans whose requests need at most kSmallTreeLevels radix-16 levels
 // (16^3 chunks) and that hold at most kSmallTreeRequests requests build every
-// request's tree in one workgroup of one launch (k_batch_tree_small).
+// request's tree in one launch, four workgroups per request
+// (k_batch_tree_small).
 constexpr uint32_t kSmallTreeLevels = 3;
 constexpr uint32_t kSmallTreeRequests = 64;
 

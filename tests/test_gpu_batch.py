@@ -271,8 +271,8 @@ def test_batch_small_plans_back_to_back(rng, torch, oracle):
 @pytest.mark.parametrize("name", GENS)
 def test_batch_small_tree(rng, torch, oracle, chunk, name):
     """Small plans (at most 16^3 chunks per request, in the kernel's
-    arguments) build every request's radix-16 tree in one workgroup: one
-    request per batch with 1, 15, 16, 17, 255, 256, 257, 1000, 2049 and 4096
+    arguments) build every request's radix-16 tree in one launch (four
+    workgroups per request, which share level 2): one request per batch with 1, 15, 16, 17, 255, 256, 257, 1000, 2049 and 4096
     chunks, then all ten in one batch, some with an offset; 64-sample chunks
     (XS256 from LDS-staged tables, level 2 four lanes per source chunk) and
     192 (no power of two: the global digit tables).  Every sample and every
