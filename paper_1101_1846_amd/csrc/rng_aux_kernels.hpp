@@ -111,9 +111,10 @@ __global__ __launch_bounds__(WG) void k_tree_stride(uint32_t *__restrict__ ws, u
 // writes them out, and the workgroups share level 2, so no workgroup waits
 // for another.  XS256 with a power-of-two unit stages the bit tables of
 // levels 0 and 1 in LDS and runs level 2 by the four-lane scheme of
-// k_tree_stride, 64 values of r per workgroup.
+// k_tree_stride, 64 values of r per workgroup; other units give every
+// level-2 thread a lane of its own.
 constexpr uint32_t kTreeHeadThreads = 4096;  // threads the head kernel starts (levels 0 .. 2)
-constexpr unsigned kTreeHeadBlocksXs256 = 4;
+constexpr unsigned kTreeHeadBlocksXs256 = 4;  // workgroups of the four-lane level 2
 
 template <class G>
 constexpr int tree_head_wg()
@@ -207,8 +208,9 @@ int launch_tree_head_t(const uint32_t *st0, uint32_t *ws, uint64_t T, uint64_t u
 {
     constexpr int WG = tree_head_wg<G>();
     const uint64_t n = T < kTreeHeadThreads ? T : kTreeHeadThreads;
+    const bool stride4 = G::kId == G_XS256 && unit && (unit & (unit - 1)) == 0;  // level 2 on four workgroups
     unsigned blocks = 1;
-    if (n > 256) blocks = G::kId == G_XS256 ? kTreeHeadBlocksXs256 : (unsigned)((n - 256 + WG - 1) / WG);
+    if (n > 256) blocks = stride4 ? kTreeHeadBlocksXs256 : (unsigned)((n - 256 + WG - 1) / WG);
     hipLaunchKernelGGL(k_tree_head<G>, dim3(blocks), dim3(WG), 0, stream, st0, ws, T, unit, tab);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
