@@ -31,8 +31,7 @@ __global__ __launch_bounds__(256) void k_seed(uint32_t *__restrict__ st, uint64_
 // One level of the radix-16 tree that starts the threads of a split
 // sequence: thread t in [16^l, min(16^(l+1), T)), t = q 16^l + r with q in
 // 1..15, starts where thread r starts, jumped by q 16^l unit samples; the
-// grid strides over the level.  (XS256 with a power-of-two unit takes
-// k_tree_stride below.)
+// grid strides over the level.  (XS256 takes k_tree_stride below.)
 constexpr int kTreeWG = 1024;
 
 template <class G>
@@ -81,27 +80,91 @@ __device__ __forceinline__ void tree_stride4(G &g, uint32_t *__restrict__ ws, ui
 // table past it is never applied (a thread it would start lies beyond T).
 __host__ __device__ constexpr uint32_t stride4_first_table(uint32_t b) { return b < 61 ? b : 61; }
 
+// Tables of M^D, M^(2D), M^(4D) (XS256) for a jump D that is no power of
+// two, built by the workgroup in LDS: lanes c < 256 carry column c of the
+// identity through the global digit tables of M^(d 16^j) for the nonzero
+// hexadecimal digits of D (each staged in t[1] first), which gives the
+// columns of M^D; each table is then built from its columns (entry v of
+// nibble p: the XOR of columns 4p + k over the set bits k of v), and the
+// columns of M^(2D) and M^(4D) are those of the previous power times its own
+// table.  t holds three tables of 2048 quads, cols 256 x 8 words.
+__device__ __forceinline__ void xs256_cols_to_table(uint4 *t, const uint32_t *cols, uint32_t tid, uint32_t wg)
+{
+    for (uint32_t q = tid; q < 2048; q += wg) {
+        const uint32_t p = q >> 5, h = (q >> 4) & 1, v = q & 15;
+        uint32_t r[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if ((v >> k) & 1)
+#pragma unroll
+                for (int w = 0; w < 4; ++w) r[w] ^= cols[(4 * p + k) * 8 + 4 * h + w];
+        t[q] = make_uint4(r[0], r[1], r[2], r[3]);
+    }
+}
+
+template <int WG>
+__device__ void xs256_power_tables(uint64_t D, uint4 *t, uint32_t *cols, const DevTables &tab)
+{
+    const uint32_t tid = threadIdx.x;
+    const bool colt = tid < 256;  // lane c carries column c
+    uint32_t col[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) col[i] = (uint32_t)(tid / 32 == (uint32_t)i) << (tid % 32);
+    for (int j = 0; j < 16; ++j) {
+        const uint32_t d = (uint32_t)(D >> (4 * j)) & 15u;  // uniform
+        if (!d) continue;
+        __syncthreads();  // the previous digit's table is read
+        stage_quads<WG, 2048>(t + 2048, tab.xs256_t4w + ((size_t)j * 15 + (d - 1)) * 2048);
+        __syncthreads();
+        if (colt) gf2_apply256_t4(t + 2048, col);
+    }
+    for (int e = 0; e < 3; ++e) {
+        if (e) {
+            if (colt) gf2_apply256_t4(t + (e - 1) * 2048, col);  // columns of M^(2^e D)
+        }
+        __syncthreads();  // the digit table, or the previous table's build, is done with
+        if (colt)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) cols[tid * 8 + i] = col[i];
+        __syncthreads();
+        xs256_cols_to_table(t + e * 2048, cols, tid, WG);
+        __syncthreads();
+    }
+}
+
 // Workgroups of 256 lanes (64 values of r, one wave per k) for small
 // levels, spread over many CUs; of 1024 lanes once the level fills every CU
 // with them (16 waves sharing the tables and hiding each other's latency).
+// b: the tables are M^(2^(b + i)) (a power-of-two unit), or with b = 64 the
+// workgroup builds the tables of M^(lo unit 2^i) itself (xs256_power_tables,
+// about 20 us, against some 7 global digit-table products for each thread
+// of the level without them).
 constexpr unsigned kStrideMaxBlocks = 2048;
+constexpr uint32_t kStrideBuild = 64;
 
 template <class G, int WG>
 __global__ __launch_bounds__(WG) void k_tree_stride(uint32_t *__restrict__ ws, uint64_t T, uint32_t shift,
-                                                   uint32_t b, DevTables tab)
+                                                   uint32_t b, uint64_t unit, DevTables tab)
 {
     constexpr int RPB = WG / 4;  // values of r per workgroup
     __shared__ uint4 s_t[3 * 2048];
-    const uint32_t b1 = stride4_first_table(b);
-    stage_quads<WG, 3 * 2048>(s_t, tab.xs256_t4 + (size_t)b1 * 2048);
-    __syncthreads();
+    __shared__ uint32_t s_col[256 * 8];
     const uint64_t lo = (uint64_t)1 << shift, hi = min(lo << 4, T);
+    const uint4 *tb = s_t;
+    if (b < kStrideBuild) {  // uniform
+        const uint32_t b1 = stride4_first_table(b);
+        stage_quads<WG, 3 * 2048>(s_t, tab.xs256_t4 + (size_t)b1 * 2048);
+        __syncthreads();
+        tb = s_t + (b - b1) * 2048;
+    } else {
+        xs256_power_tables<WG>(lo * unit, s_t, s_col, tab);
+    }
     const uint64_t nr = min(lo, hi - lo);  // threads below lo with a successor
     const uint32_t k = (threadIdx.x >> 6) & 3, off = (threadIdx.x >> 8) * 64 + (threadIdx.x & 63);
     for (uint64_t r = (uint64_t)blockIdx.x * RPB + off; r < nr; r += (uint64_t)gridDim.x * RPB) {
         G g;
         g.load(ws, T, r, tab);
-        tree_stride4(g, ws, T, r, k, shift, hi, s_t + (b - b1) * 2048);
+        tree_stride4(g, ws, T, r, k, shift, hi, tb);
     }
 }
 
@@ -246,16 +309,18 @@ int launch_tree_level_t(uint32_t *ws, uint64_t T, uint32_t shift, uint64_t unit,
 {
     const uint64_t lo = (uint64_t)1 << shift, hi = (lo << 4) < T ? (lo << 4) : T;
     if constexpr (G::kId == G_XS256) {
-        if (unit && (unit & (unit - 1)) == 0 && hi > lo) {  // (lo * unit < 2^64: the caller checked T * unit)
+        if (unit && hi > lo) {  // (lo * unit < 2^64: the caller checked T * unit)
             const uint64_t nr = hi - lo < lo ? hi - lo : lo;
-            const uint32_t b = (uint32_t)__builtin_ctzll(unit) + shift;
+            const uint32_t b =
+                (unit & (unit - 1)) == 0 ? (uint32_t)__builtin_ctzll(unit) + shift : kStrideBuild;
             if (nr >= 256 * 256) {
                 const uint64_t want = (nr + 255) / 256;
                 const unsigned blocks = want < kStrideMaxBlocks ? (unsigned)want : kStrideMaxBlocks;
-                hipLaunchKernelGGL((k_tree_stride<G, 1024>), dim3(blocks), dim3(1024), 0, stream, ws, T, shift, b, tab);
+                hipLaunchKernelGGL((k_tree_stride<G, 1024>), dim3(blocks), dim3(1024), 0, stream, ws, T, shift, b, unit,
+                                   tab);
             } else {
                 hipLaunchKernelGGL((k_tree_stride<G, 256>), dim3((unsigned)((nr + 63) / 64)), dim3(256), 0, stream, ws,
-                                   T, shift, b, tab);
+                                   T, shift, b, unit, tab);
             }
             return hipGetLastError() == hipSuccess ? 0 : -1;
         }

@@ -232,8 +232,10 @@ def test_split_parity(rng, torch, oracle, name, total, threads):
 
 # Thread counts at the edges of the start tree's levels (16^2 and 16^3: the
 # one-launch head and the level kernels; 4 * 16^3 - 1: a level whose source
-# threads are not all used), with power-of-two and odd samples per thread.
-TREE_EDGE_T = [255, 256, 257, 4095, 4096, 4097, 16383, 65535, 65537]
+# threads are not all used; 2^18 + 3: a level of 2^16 source threads, on
+# 1024-lane workgroups), with power-of-two and odd samples per thread (XS256
+# levels then build their jump tables in each workgroup).
+TREE_EDGE_T = [255, 256, 257, 4095, 4096, 4097, 16383, 65535, 65537, (1 << 18) + 3]
 
 
 @pytest.mark.parametrize("name", GENS)
