@@ -416,6 +416,58 @@ def test_rotated_rows_full_queue(rng, torch, oracle, name, S):
     assert np.array_equal(_host(st), ref_st)
 
 
+# Rows that end in a partial tile (whole 64-stream groups, 16-byte rows): N
+# mod 128 = 4, 64, 124 and 104, and every launch shape (the 32-sample tiles
+# of 512- and 1024-lane workgroups included).
+RAGGED_ROWS = [(1024, 132), (4096, 192), (64 * 2048, 252), (1 << 17, 1000)]
+
+
+@pytest.mark.parametrize("name", GENS)
+@pytest.mark.parametrize("dt", ["u32", "f32"])
+@pytest.mark.parametrize("S,N", RAGGED_ROWS)
+def test_ragged_rows(rng, torch, oracle, name, dt, S, N):
+    """Two calls in a row: every sample and the written-back states."""
+    g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
+    t = rng.DTYPES[dt]
+    st = _dev_state(torch, rng, g, 23, S)
+    ref_st = oracle.seed(o, 23, S)
+    for _ in range(2):
+        out = _gen(torch, rng, g, st, S, N, t)
+        ref = oracle.generate(o, ref_st, N, t, threads=16)
+        assert np.array_equal(out.view(np.uint32), ref.view(np.uint32)), (name, dt, S, N)
+        assert np.array_equal(_host(st), ref_st)
+        del out, ref
+
+
+@pytest.mark.parametrize("name", GENS)
+@pytest.mark.parametrize("shape", [(64, 1), (128, 16), (256, 4), (512, 8), (1024, 2)])
+def test_ragged_rows_every_shape(rng, torch, oracle, name, shape):
+    """4096 streams x 1000 samples (7 whole tiles and 104 samples) at several
+    launch shapes: every sample and the written-back states."""
+    g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
+    S, N = 4096, 1000
+    st = _dev_state(torch, rng, g, 24, S)
+    out = _gen(torch, rng, g, st, S, N, rng.RNG_U32, shape=shape)
+    ref_st = oracle.seed(o, 24, S)
+    ref = oracle.generate(o, ref_st, N, threads=16)
+    assert np.array_equal(out, ref)
+    assert np.array_equal(_host(st), ref_st)
+
+
+@pytest.mark.parametrize("name", ["XS256", "KISS"])
+def test_ragged_rows_2p20x1000(rng, torch, oracle, name):
+    """2^20 streams x 1000 samples, rows ending in a partial tile (4 GB)."""
+    g, o = rng.GENERATORS[name], oracle.GENERATORS[name]
+    S, N = 1 << 20, 1000
+    st = _dev_state(torch, rng, g, 25, S)
+    out = _gen(torch, rng, g, st, S, N, rng.RNG_U32)
+    ref_st = oracle.seed(o, 25, S)
+    ref = oracle.generate(o, ref_st, N, threads=16)
+    assert np.array_equal(out, ref)
+    assert np.array_equal(_host(st), ref_st)
+    del out, ref
+
+
 @pytest.mark.parametrize("name", ["MWC32", "XS256", "KISS"])
 def test_long_rows_full_queue(rng, torch, oracle, name):
     """2^20 streams: every wave holds as many groups as its register queue
