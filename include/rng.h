@@ -404,6 +404,9 @@ int rng_server_reset_stats(rng_server_t *h);
  * ascending) in real time, then drain; tickets (may be NULL) receives their ids. */
 int rng_server_replay(rng_server_t *h, const double *t_arrival_s, const uint64_t *stream_ids,
                       const uint64_t *lengths, const int32_t *dtypes, uint64_t n, uint64_t *tickets);
+/* Stop the worker and free the server: batches in flight complete, pending
+ * requests that can still be admitted run, and those waiting for output
+ * memory that is never released are abandoned. */
 int rng_server_destroy(rng_server_t *h);
 
 #ifdef __cplusplus

@@ -242,7 +242,10 @@ static void worker_loop(rng_server *h)
             std::unique_lock<std::mutex> lk(h->mu);
             bool inflight = false;
             for (auto &s : h->slots) inflight |= s.busy;
-            if (h->stop && h->pending.empty() && !inflight) break;
+            // Stopping with nothing in flight: every slot was free and still
+            // nothing was admitted, so what is pending waits for output memory
+            // that no one will release; it is abandoned.
+            if (h->stop && !inflight) break;
             if (!inflight && Clock::now() - last_active >= spin) {
                 h->cv_work.wait_for(lk, std::chrono::microseconds(200));
             } else {

@@ -113,6 +113,32 @@ def test_server_admission_under_memory_pressure(rng, oracle):
         rng.rng_server_destroy(h)
 
 
+def test_server_destroy_abandons_unadmittable(rng):
+    """Without auto-release, requests beyond the output pool wait for memory
+    that the caller never releases; destroying the server then returns (the
+    batches in flight complete, the waiting requests are abandoned) instead of
+    waiting for ever."""
+    import threading
+    import time
+    gens = [rng.GENERATORS[k] for k in KINDS]
+    h = rng.rng_server_create(12, gens, 4, 256 << 10, 8, 1 << 16, inflight=2, auto_release=False)
+    tickets = [rng.rng_server_submit(h, s, 1 << 14, rng.RNG_U32) for s in range(12)]  # 64 KiB each, 4 fit
+    deadline = time.time() + 20
+    while time.time() < deadline and sum(rng.rng_server_poll(h, t)[0] for t in tickets) < 3:
+        time.sleep(0.001)
+    time.sleep(0.2)  # whatever fits the pool has completed by now
+    done_n = sum(rng.rng_server_poll(h, t)[0] for t in tickets)
+    assert 3 <= done_n < len(tickets)
+    done = threading.Event()
+
+    def destroy():
+        rng.rng_server_destroy(h)
+        done.set()
+
+    threading.Thread(target=destroy, daemon=True).start()
+    assert done.wait(20), "rng_server_destroy did not return"
+
+
 def test_server_argument_errors(rng):
     gens = [rng.GENERATORS[k] for k in KINDS]
     with pytest.raises(rng.RngError):
